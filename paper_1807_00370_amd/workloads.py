@@ -1,0 +1,167 @@
+"""Seeded synthetic inputs for block-tridiagonal Hermitian positive definite systems.
+
+This module only draws inputs; it holds none of the solver's arithmetic, so both
+the CPU oracle and the HIP path can take their inputs from here.
+
+Problem shape (paper, Section 1, Eq. (Axb) and Eq. (Data)): blocks
+``A_1..A_N`` (m x m), ``B_1..B_{N-1}`` (m x m) and right-hand sides
+``y_1..y_N`` (m x k), all complex.  Arrays use 0-based numpy storage:
+
+* ``A[j-1]``  is ``A_j``            shape ``[N, m, m]``
+* ``B[j-1]``  is ``B_j``            shape ``[N-1, m, m]``  (block row j+1, column j)
+* ``y[j-1]``  is ``y_j``            shape ``[N, m, k]``
+
+Every array is C-contiguous complex128.  Only the lower triangle and the real
+part of the diagonal of each ``A_j`` carry meaning for the solver; the
+generators still return exactly Hermitian blocks.
+
+Recipes (the synthetic stand-ins for the paper's unspecified workloads):
+
+* ``random_hpd``: ``B_j`` iid complex normal with standard deviation
+  ``1/sqrt(m)``; ``A_j = M_j M_j^H / m + (||B_{j-1}||_2 + ||B_j||_2 + margin) I``
+  with ``M_j`` iid complex normal, which makes the matrix block diagonally
+  dominant and hence Hermitian positive definite.  ``||B_0|| = ||B_N|| = 0``.
+  ``shift`` subtracts ``shift_scale * (||B_{j-1}|| + ||B_j|| + margin) I``
+  (``shift_scale=2`` makes every diagonal block indefinite).
+  ``ill=True`` replaces the margin 1 by ``1e-5 (||B_{j-1}|| + ||B_j||)``.
+* ``poisson``: the real 2D five-point Laplacian on an m x N grid,
+  ``A_j = tridiag(-1, 4, -1)``, ``B_j = -I``, with ``y`` an eigenvector
+  ``y[j, a] = sin(p a pi/(m+1)) sin(q j pi/(N+1))`` (1-based a, j).
+* ``batch_shapes``: ragged batch of (N, m, k) triples.
+
+Complex normal draws with standard deviation s put ``N(0, s^2/2)`` in the real
+and in the imaginary part, so that ``E|z|^2 = s^2``.  Draw order per system:
+``B``, then ``M``, then ``y``, then ``W``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+SEED_BASE = 180700370
+
+
+def config_seed(config_index: int, instance: int = 0) -> int:
+    """Seed of instance ``instance`` of workload ``config_index``."""
+    return SEED_BASE + 10 * config_index + instance
+
+
+def _cnormal(rng: np.random.Generator, shape, std: float) -> np.ndarray:
+    z = rng.standard_normal((2,) + tuple(shape))
+    out = np.empty(shape, dtype=np.complex128)
+    out.real = z[0]
+    out.imag = z[1]
+    out *= std / math.sqrt(2.0)
+    return out
+
+
+def spectral_norms(B: np.ndarray, chunk: int = 8192) -> np.ndarray:
+    """2-norm of every block of ``B`` (largest singular value)."""
+    out = np.empty(B.shape[0], dtype=np.float64)
+    for s in range(0, B.shape[0], chunk):
+        blk = B[s:s + chunk]
+        # largest eigenvalue of B^H B equals ||B||_2^2
+        g = np.conj(np.swapaxes(blk, 1, 2)) @ blk
+        out[s:s + chunk] = np.sqrt(np.maximum(np.linalg.eigvalsh(g)[:, -1], 0.0))
+    return out
+
+
+@dataclass
+class System:
+    A: np.ndarray
+    B: np.ndarray
+    y: np.ndarray
+    W: np.ndarray | None = None
+    meta: dict | None = None
+
+    @property
+    def N(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def m(self) -> int:
+        return self.A.shape[1]
+
+    @property
+    def k(self) -> int:
+        return self.y.shape[2]
+
+
+def random_hpd(N: int, m: int, k: int, seed: int, *, margin: float = 1.0,
+               shift_scale: float = 0.0, ill: bool = False,
+               with_W: bool = False, chunk: int = 8192) -> System:
+    """The block diagonally dominant Hermitian positive definite generator."""
+    if N < 1 or m < 1 or k < 1:
+        raise ValueError("N, m, k must be >= 1")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B = _cnormal(rng, (max(N - 1, 0), m, m), 1.0 / math.sqrt(m))
+    nb = spectral_norms(B) if N > 1 else np.zeros(0)
+    left = np.zeros(N)
+    right = np.zeros(N)
+    if N > 1:
+        left[1:] = nb       # ||B_{j-1}||
+        right[:-1] = nb     # ||B_j||
+    if ill:
+        diag = (1.0 + 1e-5) * (left + right)
+    else:
+        diag = left + right + margin
+    if shift_scale:
+        diag = diag - shift_scale * (left + right + margin)
+    A = np.empty((N, m, m), dtype=np.complex128)
+    for s in range(0, N, chunk):
+        e = min(N, s + chunk)
+        M = _cnormal(rng, (e - s, m, m), 1.0)
+        blk = M @ np.conj(np.swapaxes(M, 1, 2))
+        blk /= m
+        blk = 0.5 * (blk + np.conj(np.swapaxes(blk, 1, 2)))
+        idx = np.arange(m)
+        blk[:, idx, idx] = blk[:, idx, idx].real + diag[s:e, None]
+        A[s:e] = blk
+    y = _cnormal(rng, (N, m, k), 1.0)
+    W = _cnormal(rng, (N, m, k), 1.0) if with_W else None
+    return System(A, B, y, W, dict(kind="random_hpd", N=N, m=m, k=k, seed=seed,
+                                   margin=margin, shift_scale=shift_scale, ill=ill))
+
+
+def poisson(N: int, m: int, p: int = 1, q: int = 1) -> System:
+    """Block 2D Poisson system with an eigenvector right-hand side (k = 1).
+
+    Returns the eigenvalue as ``meta['lam']``; the exact solution is
+    ``y / lam``.
+    """
+    A1 = 4.0 * np.eye(m) - np.eye(m, k=1) - np.eye(m, k=-1)
+    A = np.broadcast_to(A1, (N, m, m)).astype(np.complex128)
+    B = np.broadcast_to(-np.eye(m), (max(N - 1, 0), m, m)).astype(np.complex128)
+    a = np.arange(1, m + 1)
+    j = np.arange(1, N + 1)
+    ya = np.sin(p * a * math.pi / (m + 1))
+    yj = np.sin(q * j * math.pi / (N + 1))
+    y = (yj[:, None] * ya[None, :])[:, :, None].astype(np.complex128)
+    lam = 4.0 - 2.0 * math.cos(p * math.pi / (m + 1)) - 2.0 * math.cos(q * math.pi / (N + 1))
+    return System(np.ascontiguousarray(A), np.ascontiguousarray(B), y, None,
+                  dict(kind="poisson", N=N, m=m, k=1, p=p, q=q, lam=lam))
+
+
+def batch_shapes(count: int, seed: int, n_half_range=(128, 4096),
+                 m_choices=(8, 16, 32, 64), k_choices=(1, 4, 16)):
+    """Ragged batch: N = 2*U{lo..hi}, m and k uniform over the choices."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Ns = 2 * rng.integers(n_half_range[0], n_half_range[1] + 1, size=count)
+    ms = rng.choice(np.asarray(m_choices), size=count)
+    ks = rng.choice(np.asarray(k_choices), size=count)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(Ns, ms, ks)]
+
+
+def batch_systems(shapes, seed: int, **kw):
+    """One ``random_hpd`` system per (N, m, k), each with its own seed."""
+    return [random_hpd(N, m, k, seed * 1000 + i, **kw) for i, (N, m, k) in enumerate(shapes)]
+
+
+# The named workloads (sizes as the paper's problem statement instantiates them)
+TINY = dict(N=64, m=4, k=1)                 # one system, plus an indefinite twin
+LARGE = dict(N=65536, m=32, k=16)           # large single system
+POISSON = dict(N=4096, m=256, k=1)          # real block 2D Poisson
+DIFF = dict(N=16384, m=64, k=32)            # adjoint workload
+BATCH_COUNT = 512                           # ragged batch size

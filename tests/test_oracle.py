@@ -1,0 +1,338 @@
+"""Pins of the CPU oracle against things other than itself (CPU only).
+
+Each test names the paper passage it exercises.  The pins: dense solves
+(numpy LAPACK), dense Schur complements, LAPACK banded Cholesky (scipy
+``solveh_banded``), the closed-form 2D Poisson eigen-solution, eigenvalue
+signs for the positive-definiteness flag, hand-derived scalar values
+(``tests/golden``), finite differences and a dense autograd reference for the
+adjoint.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_1807_00370_amd import workloads as W
+from tests._dense import dense, herm_block, rel_err, stack
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SOLVERS = [oracle.solve_cr, oracle.solve_pcr, oracle.solve_thomas]
+
+
+def _sys(N, m, k, seed, **kw):
+    return W.random_hpd(N, m, k, seed, **kw)
+
+
+# ---------------------------------------------------------------- Eq. (Axb): x = A^{-1} y
+
+@pytest.mark.parametrize("N,m,k", [(1, 3, 2), (2, 2, 1), (3, 1, 1), (5, 3, 2), (8, 4, 1),
+                                   (13, 2, 3), (16, 4, 2), (31, 3, 1), (64, 4, 1)])
+@pytest.mark.parametrize("solver", SOLVERS, ids=["cr", "pcr", "thomas"])
+def test_matches_dense_solve(N, m, k, solver):
+    s = _sys(N, m, k, 1000 + N * 7 + m)
+    D = dense(s.A, s.B)
+    xd = np.linalg.solve(D, stack(s.y)).reshape(N, m, k)
+    x, info = solver(s.A, s.B, s.y)
+    assert info["status"] == 0 and info["level"] == -1 and info["block"] == -1
+    assert rel_err(x, xd) < 1e-12
+
+
+@pytest.mark.parametrize("solver", SOLVERS, ids=["cr", "pcr", "thomas"])
+@pytest.mark.parametrize("N,m,k", [(2048, 8, 4), (1001, 1, 3), (777, 5, 2)])
+def test_matches_lapack_banded(N, m, k, solver):
+    """LAPACK banded Hermitian Cholesky (zpbsv via solveh_banded), lower form."""
+    s = _sys(N, m, k, 77 + N)
+    D = None
+    n = N * m
+    u = 2 * m - 1 if m > 1 else 1
+    ab = np.zeros((u + 1, n), dtype=np.complex128)
+    # lower band storage: ab[i - j, j] = D[i, j] for i >= j
+    for j in range(N):
+        h = herm_block(s.A[j])
+        for a in range(m):
+            for b in range(a + 1):
+                ab[a - b, j * m + b] = h[a, b]
+    for j in range(N - 1):
+        for a in range(m):
+            for b in range(m):
+                ab[(j + 1) * m + a - (j * m + b), j * m + b] = s.B[j][a, b]
+    xb = scipy.linalg.solveh_banded(ab, stack(s.y), lower=True).reshape(N, m, k)
+    x, info = solver(s.A, s.B, s.y)
+    assert info["status"] == 0
+    assert rel_err(x, xb) < 1e-12
+    assert oracle.rel_residual(s.A, s.B, x, s.y) < 1e-13
+    del D
+
+
+def test_three_solvers_agree_ragged_levels():
+    """N with odd sizes at several levels (1000 -> 500 -> 250 -> 125 -> 62 ...)."""
+    s = _sys(1000, 6, 3, 5)
+    xs = [f(s.A, s.B, s.y)[0] for f in SOLVERS]
+    assert rel_err(xs[0], xs[2]) < 1e-12
+    assert rel_err(xs[1], xs[2]) < 1e-12
+
+
+# --------------------------------------------- Section 2: the split of Eq. (Formulas)
+
+@pytest.mark.parametrize("N,m,k", [(2, 2, 1), (6, 3, 2), (10, 4, 3), (16, 2, 1)])
+def test_split_equals_dense_schur(N, m, k):
+    """U = D1 - C^H D2^{-1} C, u = y_o - C^H D2^{-1} y_e (Eq. (odd)) and
+    V = D2 - C D1^{-1} C^H, v = y_e - C D1^{-1} y_o (Eq. (even)), assembled
+    densely from the reordered matrix; the formulas must give the same blocks
+    and the dense Schur complements must be block tridiagonal."""
+    s = _sys(N, m, k, 900 + N)
+    D = dense(s.A, s.B)
+    odd = np.concatenate([np.arange(j * m, (j + 1) * m) for j in range(0, N, 2)])
+    even = np.concatenate([np.arange(j * m, (j + 1) * m) for j in range(1, N, 2)])
+    D1 = D[np.ix_(odd, odd)]; D2 = D[np.ix_(even, even)]
+    C = D[np.ix_(even, odd)]
+    Y = stack(s.y)
+    Ud = D1 - C.conj().T @ np.linalg.solve(D2, C)
+    ud = Y[odd] - C.conj().T @ np.linalg.solve(D2, Y[even])
+    Vd = D2 - C @ np.linalg.solve(D1, C.conj().T)
+    vd = Y[even] - C @ np.linalg.solve(D1, Y[odd])
+    U, E, u, V, F, v, failed = oracle.split(s.A, s.B, s.y)
+    assert not failed
+    h = N // 2
+    scale = np.abs(D).max()
+    for X, Xd, Off in ((U, Ud, E), (V, Vd, F)):
+        for i in range(h):
+            for j in range(h):
+                blk = Xd[i * m:(i + 1) * m, j * m:(j + 1) * m]
+                if i == j:
+                    ref = X[i]
+                elif i == j + 1:
+                    ref = Off[j]
+                elif j == i + 1:
+                    ref = Off[i].conj().T
+                else:
+                    ref = np.zeros((m, m))
+                assert np.abs(blk - ref).max() < 1e-13 * scale
+    assert np.abs(u.reshape(-1, k) - ud).max() < 1e-13 * np.abs(Y).max() * 10
+    assert np.abs(v.reshape(-1, k) - vd).max() < 1e-13 * np.abs(Y).max() * 10
+
+
+def test_split_bitwise_hermitian():
+    """Section 4: reduced diagonal blocks come out exactly Hermitian."""
+    s = _sys(12, 5, 2, 3)
+    U, E, u, V, F, v, failed = oracle.split(s.A, s.B, s.y)
+    for X in (U, V):
+        for blk in X:
+            assert np.array_equal(blk, blk.conj().T)
+            assert np.all(np.diag(blk).imag == 0)
+
+
+def test_split_scalar_golden():
+    """Hand-derived split of the scalar system A_j = 1, B_j = 0.55, y_j = j."""
+    g = json.load(open(os.path.join(GOLDEN, "scalar_tridiagonal.json")))
+    N = g["N"]
+    A = np.full((N, 1, 1), g["a"], np.complex128)
+    B = np.full((N - 1, 1, 1), g["b"], np.complex128)
+    y = np.arange(1, N + 1, dtype=np.complex128).reshape(N, 1, 1)
+    U, E, u, V, F, v, failed = oracle.split(A, B, y)
+    assert not failed
+    for name, got in (("U", U), ("E", E), ("u", u), ("V", V), ("F", F), ("v", v)):
+        np.testing.assert_allclose(got.ravel().real, g[name], rtol=1e-14, atol=1e-15)
+        assert np.all(got.imag == 0)
+
+
+# ------------------------------------------------------ closed form: 2D Poisson
+
+@pytest.mark.parametrize("N,m,p,q", [(64, 16, 1, 1), (96, 12, 3, 7), (256, 32, 1, 1)])
+@pytest.mark.parametrize("solver", SOLVERS, ids=["cr", "pcr", "thomas"])
+def test_poisson_eigenvector(N, m, p, q, solver):
+    s = W.poisson(N, m, p, q)
+    x, info = solver(s.A, s.B, s.y)
+    assert info["status"] == 0
+    lam = s.meta["lam"]
+    assert rel_err(x, s.y / lam) < 1e-11
+
+
+# --------------------------------------------- positive definiteness (Section 2, 4)
+
+def test_flag_shifted_tiny_twin():
+    """Every diagonal block of the shifted twin is indefinite, so the very
+    first Cholesky (level 0, block 1) breaks down in both cyclic schedules."""
+    t = W.random_hpd(**W.TINY, seed=W.config_seed(0), shift_scale=2.0)
+    for a in t.A:
+        assert np.linalg.eigvalsh(herm_block(a))[0] < 0
+    assert np.linalg.eigvalsh(dense(t.A, t.B))[0] < 0
+    for f in SOLVERS:
+        x, info = f(t.A, t.B, t.y)
+        assert info == dict(status=1, level=0, block=1)
+        assert np.isnan(x).all()
+
+
+def test_flag_tiny_hpd():
+    s = W.random_hpd(**W.TINY, seed=W.config_seed(0))
+    assert np.linalg.eigvalsh(dense(s.A, s.B))[0] > 0
+    for f in SOLVERS:
+        x, info = f(s.A, s.B, s.y)
+        assert info["status"] == 0
+        assert oracle.rel_residual(s.A, s.B, x, s.y) < 1e-14
+
+
+def test_flag_deep_level_scalar_golden():
+    """Blockwise positive pivots, indefinite matrix: breakdown at level 2."""
+    g = json.load(open(os.path.join(GOLDEN, "scalar_tridiagonal.json")))
+    N = g["breakdown_N"]
+    A = np.ones((N, 1, 1), np.complex128)
+    B = np.full((N - 1, 1, 1), g["b"], np.complex128)
+    y = np.ones((N, 1, 1), np.complex128)
+    assert np.linalg.eigvalsh(dense(A, B))[0] < 0
+    _, i_cr = oracle.solve_cr(A, B, y)
+    _, i_pcr = oracle.solve_pcr(A, B, y)
+    _, i_th = oracle.solve_thomas(A, B, y)
+    assert i_cr == dict(status=1, **g["breakdown_cr"])
+    assert i_pcr == dict(status=1, **g["breakdown_pcr"])
+    assert i_th["status"] == 1
+    B2 = np.full((N - 1, 1, 1), 0.45, np.complex128)
+    assert np.linalg.eigvalsh(dense(A, B2))[0] > 0
+    for f in SOLVERS:
+        assert f(A, B2, y)[1]["status"] == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_flag_matches_eigenvalue_sign(seed):
+    """Random Hermitian shifts around the positive-definite boundary: the flag
+    is set exactly when the smallest eigenvalue is negative (Section 4: A is
+    positive definite iff every split system is)."""
+    rng = np.random.default_rng(seed)
+    N, m = 24, 3
+    s = _sys(N, m, 1, 4000 + seed)
+    D = dense(s.A, s.B)
+    lmin = np.linalg.eigvalsh(D)[0]
+    for delta in (-0.3, -0.05, 0.05, 0.3):
+        c = lmin + delta * abs(lmin)
+        A = s.A - c * np.eye(m)[None]
+        dmin = np.linalg.eigvalsh(dense(A, s.B))[0]
+        for f in SOLVERS:
+            _, info = f(A, s.B, s.y)
+            assert info["status"] == (1 if dmin < 0 else 0), (f.__name__, delta, dmin)
+    del rng
+
+
+# -------------------------------------------------------------- special cases
+
+def test_uncoupled_blocks():
+    """B = 0: the system decouples into x_j = A_j^{-1} y_j."""
+    s = _sys(10, 4, 2, 11)
+    B0 = np.zeros_like(s.B)
+    ref = np.stack([np.linalg.solve(herm_block(a), yy) for a, yy in zip(s.A, s.y)])
+    for f in SOLVERS:
+        x, info = f(s.A, B0, s.y)
+        assert info["status"] == 0 and rel_err(x, ref) < 1e-13
+
+
+def test_single_block():
+    s = _sys(1, 5, 3, 12)
+    ref = np.linalg.solve(herm_block(s.A[0]), s.y[0])
+    for f in SOLVERS:
+        x, _ = f(s.A, s.B, s.y)
+        assert rel_err(x[0], ref) < 1e-13
+
+
+def test_reads_lower_triangle_only():
+    """The upper triangle and the imaginary diagonal of A_j are ignored."""
+    s = _sys(9, 4, 2, 13)
+    A2 = s.A.copy()
+    iu = np.triu_indices(4, 1)
+    A2[:, iu[0], iu[1]] = 1e3 + 7j
+    A2[:, np.arange(4), np.arange(4)] += 5j
+    for f in SOLVERS:
+        x1, _ = f(s.A, s.B, s.y)
+        x2, _ = f(A2, s.B, s.y)
+        assert np.array_equal(x1, x2)
+
+
+def test_input_validation():
+    with pytest.raises(ValueError):
+        oracle.solve_cr(np.zeros((3, 2, 2)), np.zeros((1, 2, 2)), np.zeros((3, 2, 1)))
+
+
+# ------------------------------------------------------------------ the adjoint
+
+def _loss(A, B, y, Wt):
+    x, info = oracle.solve_cr(A, B, y)
+    assert info["status"] == 0
+    return float(np.sum((np.conj(Wt) * x).real))
+
+
+def test_backward_finite_differences():
+    """L = sum_j Re tr(W_j^H x_j): central differences (h = 1e-6, FP64)
+    against the block gradient formulas, in Hermitian directions for A_j and
+    general complex directions for B_j and y_j."""
+    N, m, k = 32, 4, 2
+    s = W.random_hpd(N, m, k, W.config_seed(4, 1), with_W=True)
+    x, _ = oracle.solve_cr(s.A, s.B, s.y)
+    lam, _ = oracle.solve_cr(s.A, s.B, s.W)
+    gA, gB = oracle.backward(x, lam)
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    for _ in range(6):
+        j = int(rng.integers(N))
+        E = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+        dA = np.zeros_like(s.A); dA[j] = E + E.conj().T
+        fd = (_loss(s.A + h * dA, s.B, s.y, s.W) - _loss(s.A - h * dA, s.B, s.y, s.W)) / (2 * h)
+        an = float(np.sum((np.conj(gA) * dA).real))
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+        jb = int(rng.integers(N - 1))
+        dB = np.zeros_like(s.B)
+        dB[jb] = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+        fd = (_loss(s.A, s.B + h * dB, s.y, s.W) - _loss(s.A, s.B - h * dB, s.y, s.W)) / (2 * h)
+        an = float(np.sum((np.conj(gB) * dB).real))
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+        dy = np.zeros_like(s.y)
+        dy[j] = rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k))
+        fd = (_loss(s.A, s.B, s.y + h * dy, s.W) - _loss(s.A, s.B, s.y - h * dy, s.W)) / (2 * h)
+        an = float(np.sum((np.conj(lam) * dy).real))
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+
+
+def test_backward_dense_autograd():
+    """Gradients of L through torch.linalg.solve on the assembled dense matrix
+    (CPU, complex128) equal the block formulas."""
+    torch = pytest.importorskip("torch")
+    N, m, k = 12, 3, 2
+    s = W.random_hpd(N, m, k, 31, with_W=True)
+    At = torch.tensor(s.A, requires_grad=True)
+    Bt = torch.tensor(s.B, requires_grad=True)
+    yt = torch.tensor(s.y, requires_grad=True)
+    rows = []
+    zero = torch.zeros((m, m), dtype=torch.complex128)
+    for i in range(N):
+        row = []
+        for j in range(N):
+            if i == j:
+                row.append(At[i])
+            elif i == j + 1:
+                row.append(Bt[j])
+            elif j == i + 1:
+                row.append(Bt[i].conj().T)
+            else:
+                row.append(zero)
+        rows.append(torch.cat(row, dim=1))
+    D = torch.cat(rows, dim=0)
+    x = torch.linalg.solve(D, yt.reshape(N * m, k))
+    loss = (torch.tensor(s.W).reshape(N * m, k).conj() * x).real.sum()
+    loss.backward()
+    xo, _ = oracle.solve_cr(s.A, s.B, s.y)
+    lam, _ = oracle.solve_cr(s.A, s.B, s.W)
+    gA, gB = oracle.backward(xo, lam)
+    assert rel_err(gA, At.grad.numpy()) < 1e-12
+    assert rel_err(gB, Bt.grad.numpy()) < 1e-12
+    assert rel_err(lam, yt.grad.numpy()) < 1e-12
+
+
+# ----------------------------------------------------------------- workloads
+
+def test_generator_is_hpd_and_seeded():
+    s1 = W.random_hpd(16, 3, 2, 5)
+    s2 = W.random_hpd(16, 3, 2, 5)
+    assert np.array_equal(s1.A, s2.A) and np.array_equal(s1.B, s2.B)
+    assert np.linalg.eigvalsh(dense(s1.A, s1.B))[0] > 0
+    for a in s1.A:
+        assert np.array_equal(a, a.conj().T)
