@@ -1,0 +1,178 @@
+/*
+ * crsolve.h -- block cyclic reduction for Hermitian positive definite
+ * block-tridiagonal linear systems on AMD Instinct MI355X (gfx950).
+ *
+ * The method follows "Review of Cyclic Reduction for Parallel Solution of
+ * Hermitian Positive Definite Block-Tridiagonal Linear Systems"
+ * (M. Neuenhofen, arXiv 1807.00370).
+ *
+ * Problem (Section 1, Eq. (Axb) and Eq. (Data)): for each system s of a batch,
+ * complex blocks A_1..A_N (m x m, Hermitian), B_1..B_{N-1} (m x m; B_j is the
+ * block at block row j+1, column j, and B_j^H the block at row j, column j+1)
+ * and right-hand sides y_1..y_N (m x k) are given; x_1..x_N (m x k) solve
+ * A x = y.  The matrix must be positive definite; when it is not, a block
+ * Cholesky factorization inside the reduction breaks down (Section 2,
+ * "Determination of Positive Definiteness"; Section 4) and the library
+ * reports it as data in crsolve_info, not as an error code.
+ *
+ * MEMORY LAYOUT (all device memory, interleaved complex (re, im), row-major
+ * blocks; systems of a batch are packed back to back in batch order):
+ *   A : sum_s N_s m_s^2 elements;  A_j of system s is the (j-1)-th m x m block.
+ *       Only the lower triangle and the real part of the diagonal are read
+ *       (the Hermitian reading; the strict upper triangle and Im(diag) are
+ *       ignored).
+ *   B : sum_s (N_s - 1) m_s^2 elements; B_j is the (j-1)-th block.
+ *   y, x, grad_x, grad_y : sum_s N_s m_s k_s elements; block j is m x k.
+ *   grad_A : like A (full blocks, not Hermitian-projected); grad_B : like B.
+ * Element type: CRSOLVE_C128 -> double[2], CRSOLVE_C64 -> float[2].  With
+ * CRSOLVE_PREC_FP32_REFINE the inputs and outputs are C128.
+ * Every pointer must be 16-byte aligned (C128) or 8-byte aligned (C64).
+ *
+ * OWNERSHIP: the caller owns every device buffer, including the workspace
+ * (size from crsolve_workspace_size) and the crsolve_info array (one entry per
+ * system).  The library never allocates device memory.  Inputs are read only.
+ * The factorization lives in the workspace and stays valid until the caller
+ * overwrites or frees it; a plan holds host metadata only.
+ *
+ * Every call that takes the workspace also takes its size in bytes, checked
+ * against crsolve_workspace_size.
+ *
+ * STREAMS: every call enqueues its work on the given stream (a hipStream_t
+ * passed as void*, NULL for the null stream) and returns without waiting,
+ * except where a call's comment says it synchronizes.
+ *
+ * ERRORS: every call returns CRSOLVE_OK (0) when its work was enqueued, or a
+ * negative code for synchronous errors, in which case nothing was enqueued:
+ *   CRSOLVE_EINVAL        invalid argument (sizes < 1, NULL or misaligned
+ *                         pointer, unknown enum value)
+ *   CRSOLVE_EHIP          a HIP runtime call failed
+ *   CRSOLVE_EWORKSPACE    workspace smaller than crsolve_workspace_size
+ *   CRSOLVE_EUNSUPPORTED  combination not provided (e.g. PCR with C64 or with
+ *                         FP32_REFINE, m > 64)
+ *   CRSOLVE_ESTATE        call out of order (solve before factor)
+ * Numerical status (not positive definite) is data in crsolve_info; the
+ * solution of a failed system is NaN.
+ */
+#ifndef CRSOLVE_H
+#define CRSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { CRSOLVE_C128 = 0, CRSOLVE_C64 = 1 } crsolve_dtype;
+
+/* NATIVE: every level in the dtype.  FP32_REFINE (C128 inputs only): the
+ * reduction runs in complex FP32 except for levels with at most
+ * fp64_tail_blocks blocks, which run in FP64; the solution is then refined
+ * with FP64 residuals r = y - A x until ||r||_F / ||y||_F <= rtol or
+ * max_refine corrections; a breakdown in FP32 falls back to an FP64
+ * factorization (crsolve_info.fp64_fallback = 1). */
+typedef enum { CRSOLVE_PREC_NATIVE = 0, CRSOLVE_PREC_FP32_REFINE = 1 } crsolve_precision;
+
+/* CR: one-sided reduction.  At each level the odd-position blocks are
+ * eliminated and the even system of Eq. (even) (formulas of Eq. (Formulas))
+ * is kept; the odd unknowns are recovered afterwards from the first block
+ * row of the reordered system of Section 2.
+ * PCR: Algorithm 1 as printed -- at each level both the odd system Eq. (odd)
+ * and the even system Eq. (even) are formed (every block is eliminated for
+ * its neighbours), until every block is uncoupled.  C128 and NATIVE only; it
+ * keeps no factorization (use crsolve_factor_solve). */
+typedef enum { CRSOLVE_SCHED_CR = 0, CRSOLVE_SCHED_PCR = 1 } crsolve_schedule;
+
+enum {
+    CRSOLVE_OK = 0,
+    CRSOLVE_EINVAL = -1,
+    CRSOLVE_EHIP = -2,
+    CRSOLVE_EWORKSPACE = -3,
+    CRSOLVE_EUNSUPPORTED = -4,
+    CRSOLVE_ESTATE = -5
+};
+
+typedef struct {
+    int32_t batch;            /* number of independent systems, >= 1        */
+    const int32_t *N, *m, *k; /* host arrays [batch]: N >= 1, 1 <= m <= 64,
+                                 k >= 1                                     */
+    crsolve_dtype dtype;
+    crsolve_precision precision;
+    crsolve_schedule schedule;
+    double rtol;              /* FP32_REFINE target, e.g. 1e-12             */
+    int32_t max_refine;       /* FP32_REFINE correction cap, e.g. 30        */
+    int32_t fp64_tail_blocks; /* FP32_REFINE: levels with <= this many
+                                 blocks run in FP64, e.g. 8                 */
+} crsolve_desc;
+
+/* One per system, in device memory, written by factor / solve. */
+typedef struct {
+    int32_t status;       /* 0: positive definite, solved; 1: not positive
+                             definite (a Cholesky pivot was not > 0)        */
+    int32_t level;        /* level of the first breakdown (lexicographic
+                             minimum over (level, block)), -1 if none       */
+    int64_t block;        /* 1-based index, in the original numbering, of
+                             the block row whose pivot broke down, -1       */
+    int32_t refine_iters; /* FP32_REFINE: corrections applied               */
+    int32_t fp64_fallback;/* FP32_REFINE: 1 if FP32 broke down and the
+                             factorization was redone in FP64               */
+    double rel_residual;  /* FP32_REFINE: final ||y - A x||_F / ||y||_F     */
+} crsolve_info;
+
+typedef struct crsolve_plan crsolve_plan;
+
+/* Validate a description and build a plan (host only, no device work).
+ * Errors: EINVAL, EUNSUPPORTED. */
+int crsolve_plan_create(const crsolve_desc *desc, crsolve_plan **out);
+
+/* Bytes of device workspace the plan needs (factors of every level, the
+ * reduced systems, right-hand-side temporaries and the level tables). */
+int crsolve_workspace_size(const crsolve_plan *plan, size_t *bytes);
+
+/* Factor: run the matrix part of every reduction level (Section 2, phase 1
+ * and 2 of the method; Eq. (Formulas) through the Section 4 recipe
+ * L = chol(M), Gt = L \ G, Z = Gt^H Gt) and store the factors in ws.
+ * info[s].status/level/block are written on the stream.  CR only.
+ * With FP32_REFINE the call synchronizes the stream once to detect an FP32
+ * breakdown and, if needed, refactors in FP64. */
+int crsolve_factor(crsolve_plan *plan, const void *A, const void *B, void *ws, size_t ws_bytes,
+                   crsolve_info *info, void *stream);
+
+/* Solve with the factors in ws: forward reduction of y through the levels,
+ * then recovery of the eliminated unknowns level by level (Section 2, phase
+ * 3).  A and B are read only by FP32_REFINE (FP64 residuals); they may be
+ * NULL otherwise.  Systems whose factorization failed get NaN in x.
+ * The solve uses a scratch region of ws that the factors do not occupy, so
+ * two solves on the same ws must not overlap in time.  With
+ * FP32_REFINE the call synchronizes the stream once per correction to test
+ * convergence and writes refine_iters and rel_residual.  CR only. */
+int crsolve_solve(const crsolve_plan *plan, void *ws, size_t ws_bytes, const void *A,
+                  const void *B, const void *y, void *x, crsolve_info *info, void *stream);
+
+/* Factor and solve in one pass over the levels (the right-hand side is
+ * reduced together with the matrix).  Equivalent to crsolve_factor followed
+ * by crsolve_solve; the only entry point of the PCR schedule. */
+int crsolve_factor_solve(crsolve_plan *plan, const void *A, const void *B, const void *y,
+                         void *ws, size_t ws_bytes, void *x, crsolve_info *info, void *stream);
+
+/* Adjoint of x = A^{-1} y for a real loss L with gradient grad_x = dL/dx
+ * (conjugate-Wirtinger convention, as PyTorch): solves A lam = grad_x with
+ * the stored factors (A is Hermitian, so A^{-H} = A^{-1}) and forms
+ *   grad_y = lam,  grad_A_j = -lam_j x_j^H,
+ *   grad_B_j = -(lam_{j+1} x_j^H + x_{j+1} lam_j^H).
+ * x must be the solution computed with these factors.  grad_y may alias
+ * nothing else.  CR and NATIVE only. */
+int crsolve_backward(const crsolve_plan *plan, void *ws, size_t ws_bytes, const void *x,
+                     const void *grad_x, void *grad_y, void *grad_A, void *grad_B, void *stream);
+
+/* Release a plan (host memory only). */
+int crsolve_plan_destroy(crsolve_plan *plan);
+
+/* Static description of an error code. */
+const char *crsolve_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRSOLVE_H */

@@ -1,0 +1,52 @@
+"""The C-ABI library loads on the CPU and exports every symbol of
+include/crsolve.h; plan creation and argument validation are host-only."""
+import os
+import re
+
+import pytest
+
+from paper_1807_00370_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "crsolve.h")).read()
+    return sorted(set(re.findall(r"\b(crsolve_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    lib = _lib.load()
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_plan_validation_host_only():
+    p = _lib.Plan([65536], [32], [16])
+    assert p.ws_bytes > 65536 * 32 * 32 * 16 * 3
+    for bad in (([0], [4], [1]), ([4], [0], [1]), ([4], [4], [0])):
+        with pytest.raises(_lib.CrsolveError) as e:
+            _lib.Plan(*bad)
+        assert e.value.code == _lib.EINVAL
+    with pytest.raises(_lib.CrsolveError) as e:
+        _lib.Plan([8], [65], [1])
+    assert e.value.code == _lib.EUNSUPPORTED
+    with pytest.raises(_lib.CrsolveError) as e:
+        _lib.Plan([8], [4], [1], dtype=_lib.C64, schedule=_lib.SCHED_PCR)
+    assert e.value.code == _lib.EUNSUPPORTED
+    assert _lib.error_string(_lib.EWORKSPACE) == "workspace too small"
+
+
+def test_null_pointers_rejected_without_device_work():
+    import ctypes
+    p = _lib.Plan([8], [4], [1])
+    lib = _lib.load()
+    assert lib.crsolve_factor(p._h, None, None, None, p.ws_bytes, None, None) == _lib.EINVAL
+    assert lib.crsolve_solve(p._h, None, p.ws_bytes, None, None, None, None, None, None) == \
+        _lib.EINVAL
+    fake = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced: size check fails first
+    assert lib.crsolve_factor(p._h, fake, fake, fake, p.ws_bytes - 1, None, None) == \
+        _lib.EWORKSPACE
+    assert lib.crsolve_factor(None, fake, fake, fake, p.ws_bytes, None, None) == _lib.EINVAL

@@ -1,0 +1,240 @@
+"""Parity of the HIP path with the FP64 oracle (GPU).
+
+Every case calls the library through its C ABI (ctypes binding) and compares
+with ``oracle/`` on the same seeded inputs: flags bit-exact, solutions
+element by element within the FP64 tolerance (max |x - x_ref| <= 1e-11
+max |x_ref|, derived in the design notes from kappa <= 10 and the depth of
+the reduction), relative residual ||y - A x||_F / ||y||_F <= 1e-12.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_00370_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32 = 2e-4
+RES64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev(cuda_ok):
+    import torch
+    from paper_1807_00370_amd import _lib
+    _lib.load()
+    return torch, torch.device("cuda:0")
+
+
+def _gpu(torch, dev, *arrs, dtype=None):
+    out = []
+    for a in arrs:
+        t = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        if dtype is not None:
+            t = t.to(dtype)
+        out.append(t)
+    return out
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _info(rec):
+    return dict(status=int(rec["status"]), level=int(rec["level"]), block=int(rec["block"]))
+
+
+def _solve(torch, dev, s, schedule="cr", dtype=None):
+    from paper_1807_00370_amd.solver import Solver
+    dt = dtype or torch.complex128
+    A, B, y = _gpu(torch, dev, s.A, s.B, s.y, dtype=dt)
+    sol = Solver([s.N], [s.m], [s.k], dtype=dt, schedule=schedule, device=dev)
+    x = sol.factor_solve(A, B, y)
+    torch.cuda.synchronize()
+    return x.cpu().numpy().astype(np.complex128), _info(sol.info_host()[0])
+
+
+CASES = [(1, 5, 3), (2, 3, 1), (3, 4, 2), (5, 2, 2), (64, 4, 1), (64, 1, 1), (1000, 6, 3),
+         (777, 16, 16), (513, 32, 16), (300, 64, 32), (129, 8, 16), (50, 17, 5), (33, 64, 1),
+         (257, 3, 7)]
+
+
+@pytest.mark.parametrize("N,m,k", CASES)
+def test_cr_matches_oracle(torch_dev, N, m, k):
+    torch, dev = torch_dev
+    print("case cr N=%d m=%d k=%d" % (N, m, k), flush=True)
+    s = W.random_hpd(N, m, k, 7000 + N + 13 * m + k)
+    x, info = _solve(torch, dev, s)
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert info == io
+    assert _rel(x, xo) <= TOL64
+    assert oracle.rel_residual(s.A, s.B, x, s.y) <= RES64
+
+
+@pytest.mark.parametrize("N,m,k", [(1, 4, 1), (2, 3, 2), (7, 4, 1), (64, 4, 1), (100, 8, 3),
+                                   (255, 16, 4), (130, 32, 16), (40, 64, 2)])
+def test_pcr_matches_oracle(torch_dev, N, m, k):
+    torch, dev = torch_dev
+    print("case pcr N=%d m=%d k=%d" % (N, m, k), flush=True)
+    s = W.random_hpd(N, m, k, 8000 + N + m)
+    x, info = _solve(torch, dev, s, schedule="pcr")
+    xo, io = oracle.solve_pcr(s.A, s.B, s.y)
+    assert info == io
+    assert _rel(x, xo) <= TOL64
+    assert oracle.rel_residual(s.A, s.B, x, s.y) <= RES64
+
+
+def test_tiny_workload_and_indefinite_twin(torch_dev):
+    torch, dev = torch_dev
+    s = W.random_hpd(**W.TINY, seed=W.config_seed(0))
+    t = W.random_hpd(**W.TINY, seed=W.config_seed(0), shift_scale=2.0)
+    for sched, ref in (("cr", oracle.solve_cr), ("pcr", oracle.solve_pcr)):
+        x, info = _solve(torch, dev, s, schedule=sched)
+        xo, io = ref(s.A, s.B, s.y)
+        assert info == io == dict(status=0, level=-1, block=-1)
+        assert _rel(x, xo) <= TOL64
+        xt, it = _solve(torch, dev, t, schedule=sched)
+        _, iot = ref(t.A, t.B, t.y)
+        assert it == iot == dict(status=1, level=0, block=1)
+        assert np.isnan(xt).all()
+
+
+def test_deep_breakdown_scalar(torch_dev):
+    """A_j = 1, B_j = 0.55, N = 64: positive blocks, indefinite matrix; the
+    first non-positive pivot appears at level 2, original block 4."""
+    torch, dev = torch_dev
+    N = 64
+    s = W.System(np.ones((N, 1, 1), np.complex128), np.full((N - 1, 1, 1), 0.55, np.complex128),
+                 np.ones((N, 1, 1), np.complex128))
+    for sched, ref in (("cr", oracle.solve_cr), ("pcr", oracle.solve_pcr)):
+        x, info = _solve(torch, dev, s, schedule=sched)
+        _, io = ref(s.A, s.B, s.y)
+        assert info == io == dict(status=1, level=2, block=4)
+        assert np.isnan(x).all()
+
+
+def test_factor_then_solve_many(torch_dev):
+    torch, dev = torch_dev
+    from paper_1807_00370_amd.solver import Solver
+    s = W.random_hpd(600, 16, 4, 321)
+    A, B, y = _gpu(torch, dev, s.A, s.B, s.y)
+    sol = Solver([s.N], [s.m], [s.k], device=dev)
+    sol.factor(A, B)
+    x1 = sol.solve(y).cpu().numpy()
+    y2 = np.ascontiguousarray(s.y[::-1])
+    x2 = sol.solve(_gpu(torch, dev, y2)[0]).cpu().numpy()
+    assert _info(sol.info_host()[0])["status"] == 0
+    xo1, _ = oracle.solve_cr(s.A, s.B, s.y)
+    xo2, _ = oracle.solve_cr(s.A, s.B, y2)
+    assert _rel(x1, xo1) <= TOL64 and _rel(x2, xo2) <= TOL64
+    xf = sol.factor_solve(A, B, y).cpu().numpy()
+    assert np.array_equal(xf, x1)
+
+
+def test_bitwise_deterministic(torch_dev):
+    torch, dev = torch_dev
+    s = W.random_hpd(2049, 32, 16, 99)
+    x1, _ = _solve(torch, dev, s)
+    x2, _ = _solve(torch, dev, s)
+    assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("N,m,k", [(64, 4, 1), (1000, 16, 4), (300, 32, 16), (100, 64, 8)])
+def test_complex64_native(torch_dev, N, m, k):
+    torch, dev = torch_dev
+    s = W.random_hpd(N, m, k, 600 + m)
+    x, info = _solve(torch, dev, s, dtype=torch.complex64)
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert info == io
+    assert _rel(x, xo) <= TOL32
+
+
+def test_ragged_batch_isolation(torch_dev):
+    """Systems of uneven N, m, k in one plan; each equals its own oracle solve,
+    and an indefinite member flags only itself."""
+    torch, dev = torch_dev
+    from paper_1807_00370_amd.solver import Solver
+    shapes = [(256, 8, 1), (300, 16, 4), (258, 32, 16), (130, 64, 4), (512, 8, 16), (2, 4, 1),
+              (1, 16, 4), (777, 3, 2), (260, 64, 1), (1024, 16, 16)]
+    systems = [W.random_hpd(N, m, k, 50 + i, shift_scale=(2.0 if i == 3 else 0.0))
+               for i, (N, m, k) in enumerate(shapes)]
+    A = np.concatenate([s.A.ravel() for s in systems])
+    B = np.concatenate([s.B.ravel() for s in systems])
+    y = np.concatenate([s.y.ravel() for s in systems])
+    sol = Solver([s.N for s in systems], [s.m for s in systems], [s.k for s in systems],
+                 device=dev)
+    At, Bt, yt = _gpu(torch, dev, A, B, y)
+    x = sol.factor_solve(At, Bt, yt).cpu().numpy()
+    infos = sol.info_host()
+    off = 0
+    for i, s in enumerate(systems):
+        n = s.y.size
+        xs = x[off:off + n].reshape(s.y.shape)
+        off += n
+        xo, io = oracle.solve_cr(s.A, s.B, s.y)
+        assert _info(infos[i]) == io, i
+        if i == 3:
+            assert io["status"] == 1 and np.isnan(xs).all()
+        else:
+            assert _rel(xs, xo) <= TOL64, i
+
+
+@pytest.mark.parametrize("N,m,k,dt", [(32, 4, 2, "c128"), (200, 16, 8, "c128"),
+                                      (64, 64, 32, "c128"), (200, 16, 8, "c64")])
+def test_backward_matches_oracle(torch_dev, N, m, k, dt):
+    torch, dev = torch_dev
+    from paper_1807_00370_amd.solver import cr_solve
+    dtype = torch.complex128 if dt == "c128" else torch.complex64
+    s = W.random_hpd(N, m, k, W.config_seed(4, 2) + N, with_W=True)
+    A, B, y, Wt = _gpu(torch, dev, s.A, s.B, s.y, s.W, dtype=dtype)
+    for t in (A, B, y):
+        t.requires_grad_(True)
+    x = cr_solve(A, B, y)
+    loss = (Wt.conj() * x).real.sum()
+    loss.backward()
+    xo, _ = oracle.solve_cr(s.A, s.B, s.y)
+    lam, _ = oracle.solve_cr(s.A, s.B, s.W)
+    gA, gB = oracle.backward(xo, lam)
+    tol = TOL64 * 10 if dt == "c128" else TOL32 * 5
+    assert _rel(A.grad.cpu().numpy(), gA) <= tol
+    assert _rel(B.grad.cpu().numpy(), gB) <= tol
+    assert _rel(y.grad.cpu().numpy(), lam) <= tol
+
+
+def test_large_single_system_full_size(torch_dev):
+    """N = 65536, m = 32, k = 16, complex128: every entry against the oracle
+    and the FP64 residual."""
+    torch, dev = torch_dev
+    print("case large N=65536 m=32 k=16", flush=True)
+    s = W.random_hpd(**W.LARGE, seed=W.config_seed(1))
+    x, info = _solve(torch, dev, s)
+    assert info == dict(status=0, level=-1, block=-1)
+    assert oracle.rel_residual(s.A, s.B, x, s.y) <= RES64
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert io["status"] == 0
+    assert _rel(x, xo) <= TOL64
+
+
+def test_invalid_arguments(torch_dev):
+    torch, dev = torch_dev
+    from paper_1807_00370_amd import _lib
+    with pytest.raises(_lib.CrsolveError) as e:
+        _lib.Plan([0], [4], [1])
+    assert e.value.code == _lib.EINVAL
+    with pytest.raises(_lib.CrsolveError) as e:
+        _lib.Plan([8], [65], [1])
+    assert e.value.code == _lib.EUNSUPPORTED
+    with pytest.raises(_lib.CrsolveError) as e:
+        _lib.Plan([8], [4], [1], dtype=_lib.C64, schedule=_lib.SCHED_PCR)
+    assert e.value.code == _lib.EUNSUPPORTED
+    p = _lib.Plan([8], [4], [1])
+    ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device=dev)
+    import ctypes
+    rc = _lib.load().crsolve_factor(p._h, None, None, ctypes.c_void_p(ws.data_ptr()),
+                                    p.ws_bytes, None, None)
+    assert rc == _lib.EINVAL
+    rc = _lib.load().crsolve_factor(p._h, ctypes.c_void_p(ws.data_ptr()),
+                                    ctypes.c_void_p(ws.data_ptr()),
+                                    ctypes.c_void_p(ws.data_ptr()), p.ws_bytes - 1, None, None)
+    assert rc == _lib.EWORKSPACE
