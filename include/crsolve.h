@@ -165,6 +165,23 @@ int crsolve_factor_solve(crsolve_plan *plan, const void *A, const void *B, const
 int crsolve_backward(const crsolve_plan *plan, void *ws, size_t ws_bytes, const void *x,
                      const void *grad_x, void *grad_y, void *grad_A, void *grad_B, void *stream);
 
+/* Per-kernel timing, for measurement.  While enabled, every launch the plan
+ * makes is bracketed by two HIP events recorded on the launch's stream (the
+ * events come from a pool owned by the plan; no device memory is allocated).
+ * crsolve_timing_enable(plan, 1) enables and clears the records, 0 disables.
+ * crsolve_timing_read waits for the last recorded event and fills up to cap
+ * entries, one per kernel name, with the number of launches and the summed
+ * event-measured durations since the last enable; *n receives the number of
+ * kernel names. */
+typedef struct {
+    char name[32];
+    int32_t launches;
+    double total_ms;
+} crsolve_kernel_time;
+
+int crsolve_timing_enable(crsolve_plan *plan, int enable);
+int crsolve_timing_read(crsolve_plan *plan, crsolve_kernel_time *out, int cap, int *n);
+
 /* Release a plan (host memory only). */
 int crsolve_plan_destroy(crsolve_plan *plan);
 

@@ -21,8 +21,8 @@ SCHED_CR, SCHED_PCR = 0, 1
 OK, EINVAL, EHIP, EWORKSPACE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
 
 EXPORTS = ("crsolve_plan_create", "crsolve_workspace_size", "crsolve_factor", "crsolve_solve",
-           "crsolve_factor_solve", "crsolve_backward", "crsolve_plan_destroy",
-           "crsolve_error_string")
+           "crsolve_factor_solve", "crsolve_backward", "crsolve_timing_enable",
+           "crsolve_timing_read", "crsolve_plan_destroy", "crsolve_error_string")
 
 
 class Desc(ctypes.Structure):
@@ -50,6 +50,11 @@ INFO_DTYPE = np.dtype([("status", "<i4"), ("level", "<i4"), ("block", "<i8"),
 assert INFO_DTYPE.itemsize == ctypes.sizeof(Info) == 32
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32),
+                ("total_ms", ctypes.c_double)]
+
+
 class CrsolveError(RuntimeError):
     def __init__(self, fn, code):
         super().__init__("%s failed: %d (%s)" % (fn, code, error_string(code)))
@@ -74,6 +79,9 @@ def load():
     lib.crsolve_solve.argtypes = [P, P, S, P, P, P, P, P, P]
     lib.crsolve_factor_solve.argtypes = [P, P, P, P, P, S, P, P, P]
     lib.crsolve_backward.argtypes = [P, P, S, P, P, P, P, P, P]
+    lib.crsolve_timing_enable.argtypes = [P, ctypes.c_int]
+    lib.crsolve_timing_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]
     lib.crsolve_plan_destroy.argtypes = [P]
     lib.crsolve_error_string.argtypes = [ctypes.c_int]
     lib.crsolve_error_string.restype = ctypes.c_char_p
@@ -131,6 +139,17 @@ class Plan:
     def factor_solve(self, A, B, y, ws, x, info, stream):
         check("crsolve_factor_solve", load().crsolve_factor_solve(self._h, A, B, y, ws,
                                                                   self.ws_bytes, x, info, stream))
+
+    def timing(self, enable: bool):
+        check("crsolve_timing_enable", load().crsolve_timing_enable(self._h, int(enable)))
+
+    def timing_read(self) -> dict:
+        """{kernel name: (launches, total ms)} since timing was enabled."""
+        buf = (KernelTime * 16)()
+        n = ctypes.c_int()
+        check("crsolve_timing_read", load().crsolve_timing_read(self._h, buf, 16, ctypes.byref(n)))
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
+                for i in range(min(n.value, 16))}
 
     def backward(self, ws, x, gx, gy, gA, gB, stream):
         check("crsolve_backward", load().crsolve_backward(self._h, ws, self.ws_bytes, x, gx, gy,

@@ -17,6 +17,7 @@
 
 #include "../../include/crsolve.h"
 #include "kernels.hpp"
+#include "kernels_fast.hpp"
 
 using crs::cx;
 using crs::Seg;
@@ -27,7 +28,7 @@ constexpr int kNT = 256;
 constexpr int kNumCls = 5;
 constexpr int kClsM[kNumCls] = {4, 8, 16, 32, 64};
 constexpr size_t kAlign = 256;
-constexpr int kMaxGrid = 1 << 16;
+constexpr int kMaxGrid = 1 << 16; // work-group kernels loop grid-stride above this grid
 
 int cls_of(int m)
 {
@@ -92,9 +93,61 @@ struct crsolve_plan {
     std::vector<Seg> segs;                      // host copy of the segment table
     std::vector<Launch> elim, reduce, back, grad;
     int nlevels = 0;
+
+    // per-kernel timing (crsolve_timing_enable / crsolve_timing_read)
+    mutable bool timing = false;
+    mutable std::vector<hipEvent_t> evpool;
+    mutable size_t evused = 0;
+    mutable std::vector<int> reckid; // kernel id of record i: events 2i, 2i+1
+
+    ~crsolve_plan()
+    {
+        for (hipEvent_t e : evpool)
+            (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
+
+enum KernelId { KID_ELIM, KID_REDUCE, KID_BACK, KID_GRAD, KID_FLAGS, KID_FINAL, KID_COUNT };
+const char* const kKernelName[KID_COUNT] = {"k_elim", "k_reduce", "k_back", "k_grad",
+                                            "k_flags_init", "k_finalize"};
+
+hipEvent_t pool_event(const crsolve_plan* p)
+{
+    if (p->evused == p->evpool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        p->evpool.push_back(e);
+    }
+    return p->evpool[p->evused++];
+}
+
+// Brackets one launch with two events when the plan's timing is enabled.
+struct Timed {
+    const crsolve_plan* p;
+    hipStream_t st;
+    hipEvent_t b = nullptr;
+    Timed(const crsolve_plan* pp, int kid, hipStream_t s) : p(pp), st(s)
+    {
+        if (!p->timing)
+            return;
+        hipEvent_t a = pool_event(p);
+        b = pool_event(p);
+        if (!a || !b) {
+            b = nullptr;
+            return;
+        }
+        p->reckid.push_back(kid);
+        (void)hipEventRecord(a, st);
+    }
+    ~Timed()
+    {
+        if (b)
+            (void)hipEventRecord(b, st);
+    }
+};
 
 template <class T>
 struct Disp {
@@ -103,29 +156,46 @@ struct Disp {
                      const void* iny, void* W, unsigned long long* flags, int mat, int rhs,
                      hipStream_t st)
     {
-        constexpr int PW = (MT >= 64 && sizeof(T) == 8) ? 32 : 64;
         int grid = (int)std::min<int64_t>(L.total, kMaxGrid);
-        hipLaunchKernelGGL((crs::k_elim<T, MT, kNT, PW>), dim3(grid), dim3(kNT), 0, st,
-                           segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA, (const cx<T>*)inB,
-                           (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+        if constexpr (MT <= 32) {
+            hipLaunchKernelGGL((crs::k_elim_w<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st, segs + L.seg0,
+                               L.nseg, L.total, (const cx<T>*)inA, (const cx<T>*)inB,
+                               (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+        } else {
+            constexpr int PW = sizeof(T) == 8 ? 32 : 64;
+            hipLaunchKernelGGL((crs::k_elim<T, MT, kNT, PW>), dim3(grid), dim3(kNT), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                               (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+        }
     }
     template <int MT>
     static void reduce(const Launch& L, const Seg* segs, const void* inA, const void* iny, void* W,
                        const unsigned long long* flags, int mat, int rhs, hipStream_t st)
     {
         int grid = (int)std::min<int64_t>(L.total, kMaxGrid);
-        hipLaunchKernelGGL((crs::k_reduce<T, MT, kNT>), dim3(grid), dim3(kNT), 0, st,
-                           segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA, (const cx<T>*)iny,
-                           (cx<T>*)W, flags, mat, rhs);
+        if constexpr (MT >= 16) {
+            hipLaunchKernelGGL((crs::k_reduce_m<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                               (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+        } else {
+            hipLaunchKernelGGL((crs::k_reduce<T, MT, kNT>), dim3(grid), dim3(kNT), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                               (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+        }
     }
     template <int MT>
     static void back(const Launch& L, const Seg* segs, const void* W, void* X,
                      const unsigned long long* flags, hipStream_t st)
     {
-        constexpr int PW = 32;
         int grid = (int)std::min<int64_t>(L.total, kMaxGrid);
-        hipLaunchKernelGGL((crs::k_back<T, MT, kNT, PW>), dim3(grid), dim3(kNT), 0, st,
-                           segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
+        if constexpr (MT == 16 || MT == 32) {
+            hipLaunchKernelGGL((crs::k_back_m<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st, segs + L.seg0,
+                               L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
+        } else {
+            constexpr int PW = 32;
+            hipLaunchKernelGGL((crs::k_back<T, MT, kNT, PW>), dim3(grid), dim3(kNT), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
+        }
     }
     template <int MT>
     static void grad(const Launch& L, const Seg* segs, const void* X, const void* Lam, void* gA,
@@ -162,6 +232,7 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
     const void* inA = L.from_user ? A : c.ws;
     const void* inB = L.from_user ? B : c.ws;
     const void* iny = L.from_user ? y : c.ws;
+    Timed tm(c.p, KID_ELIM, c.st);
 #define CALL(MT) Disp<T>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
@@ -172,6 +243,7 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
 {
     const void* inA = L.from_user ? A : c.ws;
     const void* iny = L.from_user ? y : c.ws;
+    Timed tm(c.p, KID_REDUCE, c.st);
 #define CALL(MT) Disp<T>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
@@ -180,6 +252,7 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
 template <class T>
 void run_back(const Ctx& c, const Launch& L, void* x)
 {
+    Timed tm(c.p, KID_BACK, c.st);
 #define CALL(MT) Disp<T>::template back<MT>(L, c.dsegs, c.ws, x, c.flags, c.st)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
@@ -188,6 +261,7 @@ void run_back(const Ctx& c, const Launch& L, void* x)
 template <class T>
 void run_grad(const Ctx& c, const Launch& L, const void* x, const void* lam, void* gA, void* gB)
 {
+    Timed tm(c.p, KID_GRAD, c.st);
 #define CALL(MT) Disp<T>::template grad<MT>(L, c.dsegs, x, lam, gA, gB, c.st)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
@@ -460,12 +534,14 @@ void finalize(const Ctx& c, crsolve_info* info)
     if (!info)
         return;
     int n = c.p->batch;
+    Timed tm(c.p, KID_FINAL, c.st);
     hipLaunchKernelGGL(k_finalize, dim3((n + 255) / 256), dim3(256), 0, c.st, c.flags, info, n);
 }
 
 void init_flags(const Ctx& c)
 {
     int n = c.p->batch;
+    Timed tm(c.p, KID_FLAGS, c.st);
     hipLaunchKernelGGL(crs::k_flags_init, dim3((n + 255) / 256), dim3(256), 0, c.st, c.flags, n);
 }
 
@@ -537,6 +613,48 @@ int crsolve_workspace_size(const crsolve_plan* p, size_t* bytes)
     if (!p || !bytes)
         return CRSOLVE_EINVAL;
     *bytes = p->ws_bytes;
+    return CRSOLVE_OK;
+}
+
+int crsolve_timing_enable(crsolve_plan* p, int enable)
+{
+    if (!p)
+        return CRSOLVE_EINVAL;
+    p->timing = enable != 0;
+    p->evused = 0;
+    p->reckid.clear();
+    return CRSOLVE_OK;
+}
+
+int crsolve_timing_read(crsolve_plan* p, crsolve_kernel_time* out, int cap, int* n)
+{
+    if (!p || !n || (cap > 0 && !out))
+        return CRSOLVE_EINVAL;
+    int cnt[KID_COUNT] = {0};
+    double ms[KID_COUNT] = {0};
+    if (!p->reckid.empty() &&
+        hipEventSynchronize(p->evpool[2 * p->reckid.size() - 1]) != hipSuccess)
+        return CRSOLVE_EHIP;
+    for (size_t i = 0; i < p->reckid.size(); ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p->evpool[2 * i], p->evpool[2 * i + 1]) != hipSuccess)
+            return CRSOLVE_EHIP;
+        cnt[p->reckid[i]] += 1;
+        ms[p->reckid[i]] += t;
+    }
+    int j = 0;
+    for (int kid = 0; kid < KID_COUNT; ++kid) {
+        if (!cnt[kid])
+            continue;
+        if (j < cap) {
+            std::memset(out[j].name, 0, sizeof(out[j].name));
+            std::strncpy(out[j].name, kKernelName[kid], sizeof(out[j].name) - 1);
+            out[j].launches = cnt[kid];
+            out[j].total_ms = ms[kid];
+        }
+        ++j;
+    }
+    *n = j;
     return CRSOLVE_OK;
 }
 

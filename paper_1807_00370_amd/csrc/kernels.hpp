@@ -91,6 +91,17 @@ __device__ __forceinline__ unsigned long long fail_key(int level, int64_t block)
     return ((unsigned long long)level << 40) | (unsigned long long)block;
 }
 
+// Row of packed lower-triangular index e (e = r (r + 1) / 2 + c, c <= r).
+__device__ __forceinline__ int tri_row(int e)
+{
+    int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    while ((r + 1) * (r + 2) / 2 <= e)
+        ++r;
+    while (r * (r + 1) / 2 > e)
+        --r;
+    return r;
+}
+
 __device__ __forceinline__ int find_seg(const Seg* __restrict__ s, int nseg, int64_t w)
 {
     int lo = 0, hi = nseg - 1;
@@ -170,13 +181,15 @@ __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int n
             }
             if (tid == 0 && sFail)
                 atomicMin(&flags[s.sys], fail_key(s.level, s.ob0 + s.obs * p));
-            for (int e = tid; e < m * m; e += NT) {
-                const int r = e / m, c = e % m;
-                Lg[e] = c <= r ? sL[r * LD + c] : cx<T>{T(0), T(0)};
+            for (int e = tid; e < m * (m + 1) / 2; e += NT) {
+                const int r = tri_row(e), c = e - r * (r + 1) / 2;
+                Lg[e] = sL[r * LD + c];
             }
         } else {
-            for (int e = tid; e < m * m; e += NT)
-                sL[(e / m) * LD + e % m] = Lg[e];
+            for (int e = tid; e < m * (m + 1) / 2; e += NT) {
+                const int r = tri_row(e), c = e - r * (r + 1) / 2;
+                sL[r * LD + c] = Lg[e];
+            }
             __syncthreads();
             for (int c = tid; c < m; c += NT)
                 sInv[c] = T(1) / sL[c * LD + c].r;
@@ -353,8 +366,6 @@ __global__ __launch_bounds__(NT) void k_reduce(const Seg* __restrict__ segs, int
                         if (a == b)
                             v.i = T(0);
                         Vo[a * m + b] = v;
-                        if (b < a)
-                            Vo[b * m + a] = cx<T>{v.r, -v.i};
                     }
                 }
             if (hasR && r + d < n) {
@@ -444,8 +455,10 @@ __global__ __launch_bounds__(NT) void k_back(const Seg* __restrict__ segs, int n
         const cx<T>* Q = W + s.oQ + t * mm;
         const cx<T>* g = W + s.og + t * mk;
         __syncthreads();
-        for (int e = tid; e < m * m; e += NT)
-            sL[(e / m) * LD + e % m] = L[e];
+        for (int e = tid; e < m * (m + 1) / 2; e += NT) {
+            const int r = tri_row(e), c = e - r * (r + 1) / 2;
+            sL[r * LD + c] = L[e];
+        }
         __syncthreads();
         for (int c = tid; c < m; c += NT)
             sInv[c] = T(1) / sL[c * LD + c].r;
