@@ -173,8 +173,12 @@ struct Disp {
                        const unsigned long long* flags, int mat, int rhs, hipStream_t st)
     {
         int grid = (int)std::min<int64_t>(L.total, kMaxGrid);
-        if constexpr (MT >= 16) {
+        if constexpr (MT == 16 || MT == 32) {
             hipLaunchKernelGGL((crs::k_reduce_m<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                               (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+        } else if constexpr (MT == 64) {
+            hipLaunchKernelGGL((crs::k_reduce_t<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else {

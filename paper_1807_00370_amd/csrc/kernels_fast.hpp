@@ -290,17 +290,21 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
                     if (r < m)
                         x[r] = yp[r * k + col];
             }
+            // forward substitution, L by broadcast from LDS; each row's sum
+            // runs on two independent chains
 #pragma unroll
             for (int r = 0; r < MT; ++r) {
                 if (r < m) {
-                    cx<T> v = x[r];
+                    cx<T> v0 = x[r], v1 = czero<T>();
 #pragma unroll
-                    for (int u = 0; u < r; ++u)
-                        msub(v, sL[r * (r + 1) / 2 + u], x[u]);
+                    for (int u = 0; u + 1 < r; u += 2) {
+                        msub(v0, sL[r * (r + 1) / 2 + u], x[u]);
+                        msub(v1, sL[r * (r + 1) / 2 + u + 1], x[u + 1]);
+                    }
+                    if (r & 1)
+                        msub(v0, sL[r * (r + 1) / 2 + r - 1], x[r - 1]);
                     const T iv = sInv[r];
-                    v.r *= iv;
-                    v.i *= iv;
-                    x[r] = v;
+                    x[r] = cx<T>{(v0.r + v1.r) * iv, (v0.i + v1.i) * iv};
                 }
             }
             if (act) {
@@ -318,8 +322,211 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
 
 // --------------------------------------------------------------- k_reduce_m
 
+// MFMA operand tile: 16 columns [c0, c0 + 16) of a row-major matrix with
+// kd rows, loaded once in the lane layout shared by the A and B operands
+// (lane l holds rows 4 s + l / 16, column c0 + l % 16, s < KS).
+template <class T, int KS>
+struct OpTile {
+    cx<T> v[KS];
+    __device__ __forceinline__ void load(const cx<T>* __restrict__ X, int ld, int ncol, int c0,
+                                         int kd)
+    {
+        const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+        const bool ok = c0 + cc < ncol;
+        const cx<T>* b = X + (kr * ld + c0 + cc);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            v[s] = (ok && 4 * s + kr < kd) ? b[4 * s * ld] : czero<T>();
+    }
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            v[s] = czero<T>();
+    }
+};
+
+// (cr, ci) += A^H B for operand tiles A (rows of the result) and B (columns).
+template <class T, int KS>
+__device__ __forceinline__ void mma_hn(typename MF<T>::v4& cr, typename MF<T>::v4& ci,
+                                       const OpTile<T, KS>& A, const OpTile<T, KS>& B)
+{
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        cr = MF<T>::mma(A.v[s].r, B.v[s].r, cr);
+        cr = MF<T>::mma(A.v[s].i, B.v[s].i, cr);
+        ci = MF<T>::mma(A.v[s].r, B.v[s].i, ci);
+        ci = MF<T>::mma(-A.v[s].i, B.v[s].r, ci);
+    }
+}
+
+// Reduced system for a kept block q with eliminated neighbours l, r:
+//   A'_q = A_q - P_l^H P_l - Q_r^H Q_r,  B'_q = -P_r^H Q_r,
+//   y'_q = y_q - P_l^H g_l - Q_r^H g_r.
+// Each 16-column operand tile is loaded from memory once and reused by every
+// output tile that needs it (NT16 = MT / 16 tiles per m x m operand).
 template <class T, int MT>
-__global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_m(const Seg* __restrict__ segs, int nseg,
+__global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs, int nseg,
+                                                    int64_t total, const cx<T>* __restrict__ inA,
+                                                    const cx<T>* __restrict__ iny,
+                                                    cx<T>* __restrict__ W,
+                                                    const unsigned long long* __restrict__ flags,
+                                                    int with_mat, int with_rhs)
+{
+    static_assert(MT == 16 || MT == 32, "one or two operand tiles");
+    using v4 = typename MF<T>::v4;
+    using Tile = OpTile<T, MT / 4>;
+    constexpr int NT16 = MT / 16, NV = NT16 * (NT16 + 1) / 2;
+    const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
+    const int64_t w = blockIdx.x;
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int q = s.k0 + (int)t * s.ks;
+    const int m = s.m, k = s.k, d = s.d, n = s.n;
+    const int l = q - d, r = q + d;
+    const bool hasL = l >= 0, hasR = r < n;
+    const int64_t tl = hasL ? (l - s.e0) / s.es : 0, tr = hasR ? (r - s.e0) / s.es : 0;
+    const int64_t oi = s.out_by_pos ? q : t;
+    const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
+    if ((flags[s.sys] >> 40) <= (unsigned long long)s.level)
+        return;
+    const cx<T>* Pl = W + s.oP + tl * mm;
+    const cx<T>* Qr = W + s.oQ + tr * mm;
+    const cx<T>* Pr = W + s.oP + tr * mm;
+    const cx<T>* gl = W + s.og + tl * mk;
+    const cx<T>* gr = W + s.og + tr * mk;
+    const v4 z4 = {0, 0, 0, 0};
+
+    // right-hand side columns beyond the first 16 are handled in later chunks
+    const int kc0 = with_rhs ? (k < 16 ? k : 16) : 0;
+    Tile X[NT16], G;
+    v4 vr[NV], vi[NV], yr[NT16], yi[NT16];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+        vr[i] = vi[i] = z4;
+#pragma unroll
+    for (int i = 0; i < NT16; ++i)
+        yr[i] = yi[i] = z4;
+
+    // phase 1: P_l^H P_l and P_l^H g_l;  phase 2: Q_r^H Q_r and Q_r^H g_r
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+        const bool on = ph == 0 ? hasL : hasR;
+        if (!on)
+            continue;
+        const cx<T>* Xm = ph == 0 ? Pl : Qr;
+        const cx<T>* Gm = ph == 0 ? gl : gr;
+#pragma unroll
+        for (int i = 0; i < NT16; ++i)
+            X[i].load(Xm, m, m, 16 * i, m);
+        if (kc0)
+            G.load(Gm, k, kc0, 0, m);
+        if (with_mat) {
+#pragma unroll
+            for (int i = 0, v = 0; i < NT16; ++i)
+#pragma unroll
+                for (int j = 0; j <= i; ++j, ++v)
+                    mma_hn<T, MT / 4>(vr[v], vi[v], X[i], X[j]);
+        }
+        if (kc0) {
+#pragma unroll
+            for (int i = 0; i < NT16; ++i)
+                mma_hn<T, MT / 4>(yr[i], yi[i], X[i], G);
+        }
+    }
+    if (with_mat) {
+        const cx<T>* Aq = inA + s.oA + q * mm;
+        cx<T>* Vo = W + s.oAo + oi * mm;
+#pragma unroll
+        for (int i = 0, v = 0; i < NT16; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j, ++v)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int a = 16 * i + MF<T>::row(kr, u), b = 16 * j + cc;
+                    if (a < m && b <= a) {
+                        const cx<T> x = Aq[a * m + b];
+                        cx<T> o{x.r - vr[v][u], x.i - vi[v][u]};
+                        if (a == b)
+                            o.i = T(0);
+                        Vo[a * m + b] = o;
+                    }
+                }
+    }
+    if (kc0) {
+        const cx<T>* yq = iny + s.oy + q * mk;
+        cx<T>* yo = W + s.oyo + oi * mk;
+#pragma unroll
+        for (int i = 0; i < NT16; ++i)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int a = 16 * i + MF<T>::row(kr, u), c = cc;
+                if (a < m && c < kc0) {
+                    const cx<T> x = yq[a * k + c];
+                    yo[a * k + c] = cx<T>{x.r - yr[i][u], x.i - yi[i][u]};
+                }
+            }
+    }
+    // phase 3: B'_q = -P_r^H Q_r (Q_r tiles are still in X when hasR)
+    if (with_mat && hasR && r + d < n) {
+        Tile Pt[NT16];
+#pragma unroll
+        for (int i = 0; i < NT16; ++i)
+            Pt[i].load(Pr, m, m, 16 * i, m);
+        cx<T>* Fo = W + s.oBo + oi * mm;
+#pragma unroll
+        for (int i = 0; i < NT16; ++i)
+#pragma unroll
+            for (int j = 0; j < NT16; ++j) {
+                v4 fr = z4, fi = z4;
+                mma_hn<T, MT / 4>(fr, fi, Pt[i], X[j]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int a = 16 * i + MF<T>::row(kr, u), b = 16 * j + cc;
+                    if (a < m && b < m)
+                        Fo[a * m + b] = cx<T>{-fr[u], -fi[u]};
+                }
+            }
+    }
+    // remaining right-hand-side chunks (k > 16)
+    if (with_rhs && k > 16) {
+        const cx<T>* yq = iny + s.oy + q * mk;
+        cx<T>* yo = W + s.oyo + oi * mk;
+        for (int c0 = 16; c0 < k; c0 += 16) {
+#pragma unroll
+            for (int i = 0; i < NT16; ++i) {
+                v4 ar = z4, ai = z4;
+                if (hasL) {
+                    Tile A1, G1;
+                    A1.load(Pl, m, m, 16 * i, m);
+                    G1.load(gl, k, k, c0, m);
+                    mma_hn<T, MT / 4>(ar, ai, A1, G1);
+                }
+                if (hasR) {
+                    Tile A1, G1;
+                    A1.load(Qr, m, m, 16 * i, m);
+                    G1.load(gr, k, k, c0, m);
+                    mma_hn<T, MT / 4>(ar, ai, A1, G1);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int a = 16 * i + MF<T>::row(kr, u), c = c0 + cc;
+                    if (a < m && c < k) {
+                        const cx<T> x = yq[a * k + c];
+                        yo[a * k + c] = cx<T>{x.r - ar[u], x.i - ai[u]};
+                    }
+                }
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- k_reduce_t
+
+template <class T, int MT>
+__global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* __restrict__ segs, int nseg,
                                                  int64_t total, const cx<T>* __restrict__ inA,
                                                  const cx<T>* __restrict__ iny,
                                                  cx<T>* __restrict__ W,
@@ -501,15 +708,16 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_back_m(const Seg* 
 #pragma unroll
                 for (int r = MT - 1; r >= 0; --r) {
                     if (r < m) {
-                        cx<T> v = x[r];
+                        cx<T> v0 = x[r], v1 = czero<T>();
 #pragma unroll
-                        for (int u = r + 1; u < MT; ++u)
+                        for (int u = r + 1; u < MT; u += 2) {
                             if (u < m)
-                                msub_ca(v, sL[u * (u + 1) / 2 + r], x[u]);
+                                msub_ca(v0, sL[u * (u + 1) / 2 + r], x[u]);
+                            if (u + 1 < MT && u + 1 < m)
+                                msub_ca(v1, sL[(u + 1) * (u + 2) / 2 + r], x[u + 1]);
+                        }
                         const T iv = sInv[r];
-                        v.r *= iv;
-                        v.i *= iv;
-                        x[r] = v;
+                        x[r] = cx<T>{(v0.r + v1.r) * iv, (v0.i + v1.i) * iv};
                     }
                 }
 #pragma unroll
