@@ -196,38 +196,48 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
                 const int r = tri_row(e), c = e - r * (r + 1) / 2;
                 sL[e] = Ap[r * m + c];
             }
-            if (lane == 0)
-                sFail = 0;
             __syncthreads();
-            // right-looking Cholesky, packed lower triangle
-            for (int c = 0; c < m; ++c) {
-                const int dc = c * (c + 1) / 2 + c;
-                const T dg = sL[dc].r;
-                const T sq = sqrt(dg);
-                const T inv = T(1) / sq;
-                for (int r = c + 1 + lane; r < m; r += 64) {
-                    cx<T> v = sL[r * (r + 1) / 2 + c];
-                    v.r *= inv;
-                    v.i *= inv;
-                    sL[r * (r + 1) / 2 + c] = v;
+            // left-looking Cholesky: lane r < m keeps row r in registers; at
+            // step c every row forms its dot product with row c of L (read by
+            // broadcast from LDS), lane c's result gives the pivot, rows
+            // below it get L[r][c], and column c is published to LDS
+            cx<T> a[MT];
+            const int rl = lane < m ? lane : 0;
+#pragma unroll
+            for (int u = 0; u < MT; ++u)
+                a[u] = (u <= rl) ? sL[rl * (rl + 1) / 2 + u] : czero<T>();
+            __syncthreads();
+            bool fail = false;
+#pragma unroll
+            for (int c = 0; c < MT; ++c) {
+                if (c < m) {
+                    cx<T> s0 = czero<T>(), s1 = czero<T>();
+#pragma unroll
+                    for (int u = 0; u + 1 < c; u += 2) {
+                        msub_cb(s0, a[u], sL[c * (c + 1) / 2 + u]);
+                        msub_cb(s1, a[u + 1], sL[c * (c + 1) / 2 + u + 1]);
+                    }
+                    if (c & 1)
+                        msub_cb(s0, a[c - 1], sL[c * (c + 1) / 2 + c - 1]);
+                    // s = -(sum_u L[r][u] conj(L[c][u])); the pivot is lane c's
+                    const cx<T> v{a[c].r + s0.r + s1.r, a[c].i + s0.i + s1.i};
+                    const T dg = __shfl(v.r, c);
+                    const T sq = sqrt(dg);
+                    const T inv = T(1) / sq;
+                    fail |= !(dg > T(0));
+                    if (lane == c)
+                        a[c] = cx<T>{sq, T(0)};
+                    else
+                        a[c] = cx<T>{v.r * inv, v.i * inv};
+                    if (lane >= c && lane < m)
+                        sL[lane * (lane + 1) / 2 + c] = a[c];
+                    if (lane == 0)
+                        sInv[c] = inv;
+                    __syncthreads();
                 }
-                __syncthreads();
-                if (lane == 0) {
-                    sL[dc] = cx<T>{sq, T(0)};
-                    sInv[c] = inv;
-                    if (!(dg > T(0)))
-                        sFail = 1;
-                }
-                const int nt = m - c - 1;
-                for (int e = lane; e < nt * (nt + 1) / 2; e += 64) {
-                    const int rr = tri_row(e), qq = e - rr * (rr + 1) / 2;
-                    const int r = c + 1 + rr, q = c + 1 + qq;
-                    cx<T> v = sL[r * (r + 1) / 2 + q];
-                    msub_cb(v, sL[r * (r + 1) / 2 + c], sL[q * (q + 1) / 2 + c]);
-                    sL[r * (r + 1) / 2 + q] = v;
-                }
-                __syncthreads();
             }
+            if (lane == 0)
+                sFail = fail;
             if (lane == 0 && sFail)
                 atomicMin(&flags[s.sys], fail_key(s.level, s.ob0 + s.obs * p));
             for (int e = lane; e < np; e += 64)
