@@ -1,24 +1,34 @@
 // Host driver and C ABI of the block cyclic reduction library (crsolve.h).
 //
 // A plan fixes, for every system of a batch, the sequence of reduction levels
-// and the layout of everything the levels write into the caller's workspace.
+// (one-sided: n_{l+1} = floor(n_l / 2) until no block is left; Algorithm 1:
+// in place with doubling neighbour distance), the precision of each level and
+// the layout of everything the levels write into the caller's workspace.
 // Each level is a handful of launches (k_elim, k_reduce; k_back on the way
-// back), one per block-size class present at that level; every launch covers
-// all systems of its class through a segment table that lives in the
-// workspace.
+// back), one per (block-size class, precision) present at that level; every
+// launch covers all its systems through a segment table in the workspace.
+//
+// The mixed-precision form adds conversion jobs (level-0 inputs to FP32, the
+// reduced system back to FP64 at the first FP64 level, the FP64 tail's
+// unknowns into the FP32 correction), the FP64 residual of Eq. (Axb) and a
+// host-driven refinement loop; a breakdown of the FP32 factorization falls
+// back to a complete FP64 plan that shares the workspace.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <vector>
 
 #include "../../include/crsolve.h"
 #include "kernels.hpp"
 #include "kernels_fast.hpp"
+#include "kernels_refine.hpp"
 
+using crs::CvtJob;
 using crs::cx;
 using crs::Seg;
 
@@ -43,26 +53,34 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Launch {
     int level;
     int cls;
-    int seg0, nseg; // slice of the segment table
-    int64_t total;  // work items
-    bool from_user; // level inputs are the caller's arrays
+    int f64;         // kernels instantiated in double (1) or float (0)
+    int seg0, nseg;  // slice of the segment table
+    int64_t total;   // work items
+    bool userAB;     // matrix inputs are the caller's arrays
+    bool userY;      // right-hand-side input is the caller's array
+    bool userX;      // unknowns are written to the caller's x
 };
 
-// Per-system level geometry (one-sided schedule): n_0 = N, n_{l+1} = n_l / 2
-// (floor), until n_l = 0.  Odd 1-based positions are eliminated at every
-// level, even ones kept; an odd count eliminates its last block too, so no
-// padding is needed.
-std::vector<int> cr_levels(int N)
-{
-    std::vector<int> n;
-    for (int v = N; v > 0; v /= 2)
-        n.push_back(v);
-    return n;
-}
+struct CvtLaunch {
+    int f64_src, f64_dst;
+    bool user_src;   // source is a caller array (level-0 inputs)
+    int which;       // 0: A, 1: B, 2: y (selects the caller array)
+    int job0, njobs;
+    int64_t total;
+};
 
-// Algorithm 1 in place: after level l position i couples with i +- 2^(l+1);
-// levels run until 2^l >= N, when every block is uncoupled (the last level
-// only factors and solves).
+// One level of one system.
+struct LevelSpec {
+    int n = 0, ne = 0, nk = 0;
+    int f64 = 1;
+    int64_t oL = 0, oP = 0, oQ = 0, og = 0, oAo = 0, oBo = 0, oyo = 0; // ws, level type
+    int64_t oA = 0, oB = 0, oy = 0;                                   // inputs, level type
+    bool userAB = false, userY = false, userX = false;
+    int64_t ox = 0, xo = 0, xs = 1;
+};
+
+// Algorithm 1 in place: levels run until 2^l >= N, when every block is
+// uncoupled (the last level only factors and solves).
 int pcr_depth(int N)
 {
     int D = 0;
@@ -70,6 +88,24 @@ int pcr_depth(int N)
         ++D;
     return D;
 }
+
+enum KernelId {
+    KID_ELIM,
+    KID_REDUCE,
+    KID_BACK,
+    KID_GRAD,
+    KID_FLAGS,
+    KID_FINAL,
+    KID_CONVERT,
+    KID_RESIDUAL,
+    KID_NORMS,
+    KID_UPDATE,
+    KID_COUNT
+};
+const char* const kKernelName[KID_COUNT] = {"k_elim",       "k_reduce",   "k_back",
+                                            "k_grad",       "k_flags_init", "k_finalize",
+                                            "k_convert",    "k_residual", "k_norms",
+                                            "k_update"};
 
 } // namespace
 
@@ -82,23 +118,35 @@ struct crsolve_plan {
     double rtol = 1e-12;
     int max_refine = 30;
     int tail = 8;
-    size_t esz = 16; // bytes of one complex element
 
-    // packed user arrays, complex-element offsets per system
+    // packed caller arrays: complex-element offsets per system
     std::vector<int64_t> offA, offB, offy;
+    int64_t totA = 0, totB = 0, toty = 0, totN = 0;
 
     // workspace layout (bytes)
-    size_t off_flags = 0, off_segs = 0, ws_bytes = 0;
+    size_t off_flags = 0, off_segs = 0, off_jobs = 0, ws_bytes = 0;
+    size_t off_part = 0, off_norms = 0, off_info = 0, off_fb = 0;
+    size_t off_d32 = 0; // refinement correction (complex FP32, like y)
 
-    std::vector<Seg> segs;                      // host copy of the segment table
-    std::vector<Launch> elim, reduce, back, grad;
+    std::vector<std::vector<LevelSpec>> lv; // per system
+    std::vector<int> sw;                    // first FP64 level per system (refine)
+    std::vector<Seg> segs;
+    std::vector<CvtJob> jobs;
+    std::vector<Launch> elim, reduce, back, grad, resid;
+    int norm_seg0 = 0;
+    std::vector<CvtLaunch> cvt_factor0, cvt_solve0;
+    std::vector<std::vector<CvtLaunch>> cvt_factor_sw, cvt_solve_sw, scatter_sw;
     int nlevels = 0;
+
+    std::unique_ptr<crsolve_plan> fb; // FP64 plan used after an FP32 breakdown
+    mutable bool use_fb = false;
 
     // per-kernel timing (crsolve_timing_enable / crsolve_timing_read)
     mutable bool timing = false;
     mutable std::vector<hipEvent_t> evpool;
     mutable size_t evused = 0;
-    mutable std::vector<int> reckid; // kernel id of record i: events 2i, 2i+1
+    mutable std::vector<int> reckid;
+    crsolve_plan* timing_parent = nullptr;
 
     ~crsolve_plan()
     {
@@ -109,9 +157,7 @@ struct crsolve_plan {
 
 namespace {
 
-enum KernelId { KID_ELIM, KID_REDUCE, KID_BACK, KID_GRAD, KID_FLAGS, KID_FINAL, KID_COUNT };
-const char* const kKernelName[KID_COUNT] = {"k_elim", "k_reduce", "k_back", "k_grad",
-                                            "k_flags_init", "k_finalize"};
+const crsolve_plan* tplan(const crsolve_plan* p) { return p->timing_parent ? p->timing_parent : p; }
 
 hipEvent_t pool_event(const crsolve_plan* p)
 {
@@ -129,7 +175,7 @@ struct Timed {
     const crsolve_plan* p;
     hipStream_t st;
     hipEvent_t b = nullptr;
-    Timed(const crsolve_plan* pp, int kid, hipStream_t s) : p(pp), st(s)
+    Timed(const crsolve_plan* pp, int kid, hipStream_t s) : p(tplan(pp)), st(s)
     {
         if (!p->timing)
             return;
@@ -149,6 +195,8 @@ struct Timed {
     }
 };
 
+unsigned grid_of(int64_t total) { return (unsigned)std::min<int64_t>(total, kMaxGrid); }
+
 template <class T>
 struct Disp {
     template <int MT>
@@ -156,15 +204,14 @@ struct Disp {
                      const void* iny, void* W, unsigned long long* flags, int mat, int rhs,
                      hipStream_t st)
     {
-        int grid = (int)std::min<int64_t>(L.total, kMaxGrid);
         if constexpr (MT <= 32) {
-            hipLaunchKernelGGL((crs::k_elim_w<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st, segs + L.seg0,
-                               L.nseg, L.total, (const cx<T>*)inA, (const cx<T>*)inB,
-                               (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_elim_w<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                               (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else {
             constexpr int PW = sizeof(T) == 8 ? 32 : 64;
-            hipLaunchKernelGGL((crs::k_elim<T, MT, kNT, PW>), dim3(grid), dim3(kNT), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+            hipLaunchKernelGGL((crs::k_elim<T, MT, kNT, PW>), dim3(grid_of(L.total)), dim3(kNT), 0,
+                               st, segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
         }
     }
@@ -172,7 +219,6 @@ struct Disp {
     static void reduce(const Launch& L, const Seg* segs, const void* inA, const void* iny, void* W,
                        const unsigned long long* flags, int mat, int rhs, hipStream_t st)
     {
-        int grid = (int)std::min<int64_t>(L.total, kMaxGrid);
         if constexpr (MT == 16 || MT == 32) {
             hipLaunchKernelGGL((crs::k_reduce_m<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
@@ -182,8 +228,8 @@ struct Disp {
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else {
-            hipLaunchKernelGGL((crs::k_reduce<T, MT, kNT>), dim3(grid), dim3(kNT), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+            hipLaunchKernelGGL((crs::k_reduce<T, MT, kNT>), dim3(grid_of(L.total)), dim3(kNT), 0,
+                               st, segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
         }
     }
@@ -191,22 +237,21 @@ struct Disp {
     static void back(const Launch& L, const Seg* segs, const void* W, void* X,
                      const unsigned long long* flags, hipStream_t st)
     {
-        int grid = (int)std::min<int64_t>(L.total, kMaxGrid);
         if constexpr (MT == 16 || MT == 32) {
-            hipLaunchKernelGGL((crs::k_back_m<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st, segs + L.seg0,
-                               L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
+            hipLaunchKernelGGL((crs::k_back_m<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
         } else {
             constexpr int PW = 32;
-            hipLaunchKernelGGL((crs::k_back<T, MT, kNT, PW>), dim3(grid), dim3(kNT), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
+            hipLaunchKernelGGL((crs::k_back<T, MT, kNT, PW>), dim3(grid_of(L.total)), dim3(kNT), 0,
+                               st, segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X,
+                               flags);
         }
     }
     template <int MT>
     static void grad(const Launch& L, const Seg* segs, const void* X, const void* Lam, void* gA,
                      void* gB, hipStream_t st)
     {
-        int grid = (int)std::min<int64_t>(L.total, kMaxGrid);
-        hipLaunchKernelGGL((crs::k_grad<T, MT, kNT>), dim3(grid), dim3(kNT), 0, st,
+        hipLaunchKernelGGL((crs::k_grad<T, MT, kNT>), dim3(grid_of(L.total)), dim3(kNT), 0, st,
                            segs + L.seg0, L.nseg, L.total, (const cx<T>*)X, (const cx<T>*)Lam,
                            (cx<T>*)gA, (cx<T>*)gB);
     }
@@ -225,17 +270,30 @@ struct Ctx {
     const crsolve_plan* p;
     char* ws;
     const Seg* dsegs;
+    const CvtJob* djobs;
     unsigned long long* flags;
     hipStream_t st;
 };
+
+Ctx make_ctx(const crsolve_plan* p, void* ws, void* stream)
+{
+    Ctx c;
+    c.p = p;
+    c.ws = (char*)ws;
+    c.dsegs = (const Seg*)(c.ws + p->off_segs);
+    c.djobs = (const CvtJob*)(c.ws + p->off_jobs);
+    c.flags = (unsigned long long*)(c.ws + p->off_flags);
+    c.st = (hipStream_t)stream;
+    return c;
+}
 
 template <class T>
 void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const void* y, int mat,
               int rhs)
 {
-    const void* inA = L.from_user ? A : c.ws;
-    const void* inB = L.from_user ? B : c.ws;
-    const void* iny = L.from_user ? y : c.ws;
+    const void* inA = L.userAB ? A : c.ws;
+    const void* inB = L.userAB ? B : c.ws;
+    const void* iny = L.userY ? y : c.ws;
     Timed tm(c.p, KID_ELIM, c.st);
 #define CALL(MT) Disp<T>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st)
     CRS_BY_CLASS(L.cls, CALL)
@@ -245,8 +303,8 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
 template <class T>
 void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int mat, int rhs)
 {
-    const void* inA = L.from_user ? A : c.ws;
-    const void* iny = L.from_user ? y : c.ws;
+    const void* inA = L.userAB ? A : c.ws;
+    const void* iny = L.userY ? y : c.ws;
     Timed tm(c.p, KID_REDUCE, c.st);
 #define CALL(MT) Disp<T>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st)
     CRS_BY_CLASS(L.cls, CALL)
@@ -256,8 +314,9 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
 template <class T>
 void run_back(const Ctx& c, const Launch& L, void* x)
 {
+    void* X = L.userX ? x : c.ws;
     Timed tm(c.p, KID_BACK, c.st);
-#define CALL(MT) Disp<T>::template back<MT>(L, c.dsegs, c.ws, x, c.flags, c.st)
+#define CALL(MT) Disp<T>::template back<MT>(L, c.dsegs, c.ws, X, c.flags, c.st)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
@@ -271,7 +330,27 @@ void run_grad(const Ctx& c, const Launch& L, const void* x, const void* lam, voi
 #undef CALL
 }
 
-__global__ void k_finalize(const unsigned long long* flags, crsolve_info* info, int n)
+void run_cvt(const Ctx& c, const CvtLaunch& L, const void* A, const void* B, const void* y)
+{
+    const void* src = L.user_src ? (L.which == 0 ? A : (L.which == 1 ? B : y)) : c.ws;
+    Timed tm(c.p, KID_CONVERT, c.st);
+    const unsigned g = (unsigned)std::min<int64_t>((L.total + 255) / 256, 1 << 16);
+    const CvtJob* jb = c.djobs + L.job0;
+    if (L.f64_src && !L.f64_dst)
+        hipLaunchKernelGGL((crs::k_convert<double, float>), dim3(g), dim3(256), 0, c.st, jb,
+                           L.njobs, L.total, (const cx<double>*)src, (cx<float>*)c.ws);
+    else if (!L.f64_src && L.f64_dst)
+        hipLaunchKernelGGL((crs::k_convert<float, double>), dim3(g), dim3(256), 0, c.st, jb,
+                           L.njobs, L.total, (const cx<float>*)src, (cx<double>*)c.ws);
+    else if (L.f64_src)
+        hipLaunchKernelGGL((crs::k_convert<double, double>), dim3(g), dim3(256), 0, c.st, jb,
+                           L.njobs, L.total, (const cx<double>*)src, (cx<double>*)c.ws);
+    else
+        hipLaunchKernelGGL((crs::k_convert<float, float>), dim3(g), dim3(256), 0, c.st, jb,
+                           L.njobs, L.total, (const cx<float>*)src, (cx<float>*)c.ws);
+}
+
+__global__ void k_finalize(const unsigned long long* flags, crsolve_info* info, int n, int fb)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -281,191 +360,395 @@ __global__ void k_finalize(const unsigned long long* flags, crsolve_info* info, 
         v.level = v.status ? (int32_t)(f >> 40) : -1;
         v.block = v.status ? (int64_t)(f & ((1ull << 40) - 1)) : -1;
         v.refine_iters = 0;
-        v.fp64_fallback = 0;
+        v.fp64_fallback = fb;
         v.rel_residual = 0.0;
         info[i] = v;
     }
 }
 
+// info[i].refine_iters / rel_residual from a host-filled table {iters, rel}.
+__global__ void k_set_refine(const double* tab, crsolve_info* info, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        info[i].refine_iters = (int32_t)tab[2 * i];
+        info[i].rel_residual = tab[2 * i + 1];
+    }
+}
+
 // ------------------------------------------------------------------ plan build
 
-// Appends launches for one phase: for each level, one launch per class with
-// work, segments contiguous in the table.  `count(s, lvl)` gives the work
-// items of system s at level lvl (0 = none); `make(s, lvl)` its segment.
-template <class Count, class Make>
-void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count count, Make make)
+struct WsAlloc {
+    size_t off = 0;
+    int64_t take(int64_t elems, size_t esz)
+    {
+        int64_t o = (int64_t)(off / esz);
+        off = align_up(off + (size_t)elems * esz);
+        return o;
+    }
+};
+
+// Appends launches: for each level, one launch per (class, precision) with
+// work; `count(s, l)` gives the work items of system s at level l.
+template <class Count>
+void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count count)
 {
     for (int lvl = 0; lvl < nlev; ++lvl)
-        for (int c = 0; c < kNumCls; ++c) {
-            Launch L{lvl, c, (int)p->segs.size(), 0, 0, lvl == 0};
-            for (int s = 0; s < p->batch; ++s) {
-                if (p->cls[s] != c)
-                    continue;
-                int64_t cnt = count(s, lvl);
-                if (cnt <= 0)
-                    continue;
-                Seg g = make(s, lvl);
-                g.w0 = L.total;
-                L.total += cnt;
-                p->segs.push_back(g);
-                ++L.nseg;
+        for (int f = 0; f < 2; ++f)
+            for (int c = 0; c < kNumCls; ++c) {
+                Launch L{lvl, c, f, (int)p->segs.size(), 0, 0, false, false, false};
+                for (int s = 0; s < p->batch; ++s) {
+                    if (p->cls[s] != c || lvl >= (int)p->lv[s].size())
+                        continue;
+                    const LevelSpec& v = p->lv[s][lvl];
+                    if (v.f64 != f)
+                        continue;
+                    int64_t cnt = count(s, lvl);
+                    if (cnt <= 0)
+                        continue;
+                    Seg g;
+                    std::memset(&g, 0, sizeof(g));
+                    g.n = v.n;
+                    g.m = p->m[s];
+                    g.k = p->k[s];
+                    g.level = lvl;
+                    g.sys = s;
+                    g.oL = v.oL; g.oP = v.oP; g.oQ = v.oQ; g.og = v.og;
+                    g.oAo = v.oAo; g.oBo = v.oBo; g.oyo = v.oyo;
+                    g.oA = v.oA; g.oB = v.oB; g.oy = v.oy;
+                    g.ox = v.ox; g.xo = v.xo; g.xs = v.xs;
+                    if (p->sched == CRSOLVE_SCHED_CR) {
+                        g.d = 1;
+                        g.e0 = 0; g.es = 2; g.ne = v.ne;
+                        g.k0 = 1; g.ks = 2; g.nk = v.nk;
+                        g.out_by_pos = 0;
+                        g.ob0 = 1ll << lvl;
+                        g.obs = 1ll << lvl;
+                    } else {
+                        g.d = (int)std::min<int64_t>(1ll << lvl, (int64_t)1 << 30);
+                        g.e0 = 0; g.es = 1; g.ne = v.ne;
+                        g.k0 = 0; g.ks = 1; g.nk = v.nk;
+                        g.out_by_pos = 1;
+                        g.ob0 = 1;
+                        g.obs = 1;
+                    }
+                    g.w0 = L.total;
+                    L.total += cnt;
+                    L.userAB = v.userAB;
+                    L.userY = v.userY;
+                    L.userX = v.userX;
+                    p->segs.push_back(g);
+                    ++L.nseg;
+                }
+                if (L.nseg)
+                    out.push_back(L);
+                else
+                    p->segs.resize(L.seg0);
             }
-            if (L.nseg)
-                out.push_back(L);
-            else
-                p->segs.resize(L.seg0);
-        }
+}
+
+// Conversion launches from a list of (src, dst, count) ranges.
+struct JobIn {
+    int64_t src, dst, count;
+};
+void add_cvt(crsolve_plan* p, std::vector<CvtLaunch>& out, const std::vector<JobIn>& in,
+             int f64_src, int f64_dst, bool user_src, int which)
+{
+    if (in.empty())
+        return;
+    CvtLaunch L{f64_src, f64_dst, user_src, which, (int)p->jobs.size(), 0, 0};
+    for (const JobIn& j : in) {
+        if (j.count <= 0)
+            continue;
+        p->jobs.push_back(CvtJob{L.total, j.src, j.dst, j.count});
+        L.total += j.count;
+        ++L.njobs;
+    }
+    if (L.njobs)
+        out.push_back(L);
+    else
+        p->jobs.resize(L.job0);
 }
 
 int build_plan(crsolve_plan* p)
 {
-    const size_t es = p->esz;
-    size_t off = 0;
-    p->off_flags = off;
-    off = align_up(off + sizeof(unsigned long long) * p->batch);
+    const bool refine = p->prec == CRSOLVE_PREC_FP32_REFINE;
+    const bool f64native = p->dtype == CRSOLVE_C128;
+    WsAlloc a;
+    p->off_flags = a.off;
+    a.off = align_up(a.off + sizeof(unsigned long long) * p->batch);
+    p->lv.assign(p->batch, {});
+    p->sw.assign(p->batch, -1);
+    const size_t e32 = sizeof(cx<float>), e64 = sizeof(cx<double>);
 
-    // per-system per-level workspace offsets (complex elements)
-    struct Lv {
-        int n, ne, nk;
-        int64_t oL, oP, oQ, og, oAo, oBo, oyo; // outputs of this level
-        int64_t oA, oB, oy;                    // inputs of this level (ws), level >= 1
-    };
-    std::vector<std::vector<Lv>> lv(p->batch);
-    auto take = [&](int64_t elems) {
-        int64_t o = (int64_t)(off / es);
-        off = align_up(off + (size_t)elems * es);
-        return o;
-    };
+    // refinement buffers: the correction d (complex FP32, laid out like y),
+    // residual norm partials and totals, the info table
+    std::vector<int64_t> oA32(p->batch, 0), oB32(p->batch, 0), or32(p->batch, 0),
+        or64(p->batch, 0), oxt(p->batch, 0);
+    if (refine) {
+        p->off_d32 = a.off;
+        a.off = align_up(a.off + (size_t)p->toty * e32);
+        p->off_part = a.off;
+        a.off = align_up(a.off + sizeof(double) * 2 * (size_t)std::max<int64_t>(p->totN, 1));
+        p->off_norms = a.off;
+        a.off = align_up(a.off + sizeof(double) * 2 * p->batch);
+        p->off_info = a.off;
+        a.off = align_up(a.off + sizeof(double) * 2 * p->batch);
+    }
+
     int maxlev = 0;
     for (int s = 0; s < p->batch; ++s) {
         const int64_t mm = (int64_t)p->m[s] * p->m[s], mk = (int64_t)p->m[s] * p->k[s];
+        std::vector<LevelSpec>& L = p->lv[s];
         if (p->sched == CRSOLVE_SCHED_CR) {
-            std::vector<int> ns = cr_levels(p->N[s]);
-            lv[s].resize(ns.size());
-            for (size_t l = 0; l < ns.size(); ++l) {
-                Lv& v = lv[s][l];
-                v.n = ns[l];
-                v.ne = (v.n + 1) / 2;
-                v.nk = v.n / 2;
-                v.oL = take(v.ne * mm);
-                v.oP = take(v.ne * mm);
-                v.oQ = take(v.ne * mm);
-                v.oAo = take(v.nk * mm);
-                v.oBo = take(std::max(v.nk - 1, 0) * mm);
+            for (int v = p->N[s]; v > 0; v /= 2) {
+                LevelSpec ls;
+                ls.n = v;
+                ls.ne = (v + 1) / 2;
+                ls.nk = v / 2;
+                ls.f64 = refine ? (v <= p->tail ? 1 : 0) : (f64native ? 1 : 0);
+                L.push_back(ls);
             }
-            // right-hand-side scratch (solve phase)
-            for (size_t l = 0; l < ns.size(); ++l) {
-                Lv& v = lv[s][l];
-                v.og = take(v.ne * mk);
-                v.oyo = take(v.nk * mk);
+            int sw = -1;
+            if (refine)
+                for (size_t l = 0; l < L.size(); ++l)
+                    if (L[l].f64) {
+                        sw = (int)l;
+                        break;
+                    }
+            p->sw[s] = sw;
+            // factor storage and reduced systems, per level in its precision
+            for (size_t l = 0; l < L.size(); ++l) {
+                LevelSpec& v = L[l];
+                const size_t es = v.f64 ? e64 : e32;
+                v.oL = a.take(v.ne * mm, es);
+                v.oP = a.take(v.ne * mm, es);
+                v.oQ = a.take(v.ne * mm, es);
+                v.oAo = a.take(v.nk * mm, es);
+                v.oBo = a.take(std::max(v.nk - 1, 0) * mm, es);
             }
-            for (size_t l = 1; l < ns.size(); ++l) {
-                lv[s][l].oA = lv[s][l - 1].oAo;
-                lv[s][l].oB = lv[s][l - 1].oBo;
-                lv[s][l].oy = lv[s][l - 1].oyo;
+            for (size_t l = 0; l < L.size(); ++l) {
+                LevelSpec& v = L[l];
+                const size_t es = v.f64 ? e64 : e32;
+                v.og = a.take(v.ne * mk, es);
+                v.oyo = a.take(v.nk * mk, es);
             }
-            maxlev = std::max<int>(maxlev, (int)ns.size());
+            // level inputs
+            for (size_t l = 0; l < L.size(); ++l) {
+                LevelSpec& v = L[l];
+                if (l == 0) {
+                    if (!refine || v.f64) {
+                        v.userAB = true;
+                        v.oA = p->offA[s];
+                        v.oB = p->offB[s];
+                    } else {
+                        oA32[s] = a.take((int64_t)p->N[s] * mm, e32);
+                        oB32[s] = a.take((int64_t)(p->N[s] - 1) * mm, e32);
+                        v.oA = oA32[s];
+                        v.oB = oB32[s];
+                    }
+                    if (!refine) {
+                        v.userY = true;
+                        v.oy = p->offy[s];
+                    } else if (v.f64) {
+                        or64[s] = a.take((int64_t)p->N[s] * mk, e64);
+                        v.oy = or64[s];
+                    } else {
+                        or32[s] = a.take((int64_t)p->N[s] * mk, e32);
+                        v.oy = or32[s];
+                    }
+                } else if ((int)l == sw) {
+                    // first FP64 level: its inputs are FP64 copies of the
+                    // previous (FP32) level's reduced system
+                    v.oA = a.take(v.n * mm, e64);
+                    v.oB = a.take(std::max(v.n - 1, 0) * mm, e64);
+                    v.oy = a.take(v.n * mk, e64);
+                } else {
+                    v.oA = L[l - 1].oAo;
+                    v.oB = L[l - 1].oBo;
+                    v.oy = L[l - 1].oyo;
+                }
+            }
+            // unknowns
+            if (refine && sw >= 0)
+                oxt[s] = a.take((int64_t)L[sw].n * mk, e64);
+            for (size_t l = 0; l < L.size(); ++l) {
+                LevelSpec& v = L[l];
+                if (!refine) {
+                    v.userX = true;
+                    v.ox = p->offy[s];
+                    v.xo = (1ll << l) - 1;
+                    v.xs = 1ll << l;
+                } else if (sw < 0 || (int)l < sw) {
+                    v.ox = (int64_t)(p->off_d32 / e32) + p->offy[s];
+                    v.xo = (1ll << l) - 1;
+                    v.xs = 1ll << l;
+                } else {
+                    v.ox = oxt[s];
+                    v.xo = (1ll << (l - sw)) - 1;
+                    v.xs = 1ll << (l - sw);
+                }
+            }
         } else {
             const int N = p->N[s], D = pcr_depth(N);
-            lv[s].resize(D + 1);
-            int64_t oL = take(N * mm), oP = take(N * mm), oQ = take(N * mm), og = take(N * mk);
+            const size_t es = e64;
+            int64_t oL = a.take(N * mm, es), oP = a.take(N * mm, es), oQ = a.take(N * mm, es),
+                    og = a.take(N * mk, es);
             int64_t bA[2], bB[2], by[2];
             for (int b = 0; b < 2; ++b) {
-                bA[b] = take(N * mm);
-                bB[b] = take(N * mm);
-                by[b] = take(N * mk);
+                bA[b] = a.take(N * mm, es);
+                bB[b] = a.take(N * mm, es);
+                by[b] = a.take(N * mk, es);
             }
             for (int l = 0; l <= D; ++l) {
-                Lv& v = lv[s][l];
+                LevelSpec v;
                 v.n = N;
                 v.ne = N;
                 v.nk = l < D ? N : 0;
+                v.f64 = 1;
                 v.oL = oL; v.oP = oP; v.oQ = oQ; v.og = og;
                 v.oAo = bA[(l + 1) & 1]; v.oBo = bB[(l + 1) & 1]; v.oyo = by[(l + 1) & 1];
-                v.oA = bA[l & 1]; v.oB = bB[l & 1]; v.oy = by[l & 1];
+                if (l == 0) {
+                    v.userAB = v.userY = true;
+                    v.oA = p->offA[s]; v.oB = p->offB[s]; v.oy = p->offy[s];
+                } else {
+                    v.oA = bA[l & 1]; v.oB = bB[l & 1]; v.oy = by[l & 1];
+                }
+                v.userX = true;
+                v.ox = p->offy[s];
+                v.xo = 0;
+                v.xs = 1;
+                L.push_back(v);
             }
-            maxlev = std::max(maxlev, D + 1);
         }
+        maxlev = std::max(maxlev, (int)L.size());
     }
     p->nlevels = maxlev;
 
-    auto seg_of = [&](int s, int l) {
-        const Lv& v = lv[s][l];
-        Seg g;
-        std::memset(&g, 0, sizeof(g));
-        g.n = v.n;
-        g.m = p->m[s];
-        g.k = p->k[s];
-        g.level = l;
-        g.sys = s;
-        g.oL = v.oL; g.oP = v.oP; g.oQ = v.oQ; g.og = v.og;
-        g.oAo = v.oAo; g.oBo = v.oBo; g.oyo = v.oyo;
-        g.oA = l == 0 ? p->offA[s] : v.oA;
-        g.oB = l == 0 ? p->offB[s] : v.oB;
-        g.oy = l == 0 ? p->offy[s] : v.oy;
-        g.ox = p->offy[s];
-        if (p->sched == CRSOLVE_SCHED_CR) {
-            g.d = 1;
-            g.e0 = 0; g.es = 2; g.ne = v.ne;
-            g.k0 = 1; g.ks = 2; g.nk = v.nk;
-            g.out_by_pos = 0;
-            g.xo = (1ll << l) - 1;
-            g.xs = 1ll << l;
-            g.ob0 = 1ll << l;
-            g.obs = 1ll << l;
-        } else {
-            g.d = (int)std::min<int64_t>(1ll << l, (int64_t)1 << 30);
-            g.e0 = 0; g.es = 1; g.ne = v.ne;
-            g.k0 = 0; g.ks = 1; g.nk = v.nk;
-            g.out_by_pos = 1;
-            g.xo = 0;
-            g.xs = 1;
-            g.ob0 = 1;
-            g.obs = 1;
-        }
-        return g;
-    };
-    auto has = [&](int s, int l) { return l < (int)lv[s].size(); };
-
     p->segs.clear();
-    p->elim.clear();
-    p->reduce.clear();
-    p->back.clear();
-    p->grad.clear();
-    add_launches(p, p->elim, maxlev,
-                 [&](int s, int l) -> int64_t { return has(s, l) ? lv[s][l].ne : 0; }, seg_of);
-    add_launches(p, p->reduce, maxlev,
-                 [&](int s, int l) -> int64_t { return has(s, l) ? lv[s][l].nk : 0; }, seg_of);
+    p->jobs.clear();
+    p->elim.clear(); p->reduce.clear(); p->back.clear(); p->grad.clear(); p->resid.clear();
+    add_launches(p, p->elim, maxlev, [&](int s, int l) -> int64_t { return p->lv[s][l].ne; });
+    add_launches(p, p->reduce, maxlev, [&](int s, int l) -> int64_t { return p->lv[s][l].nk; });
     // Recovery of the unknowns: the one-sided schedule back-substitutes at
     // every level; Algorithm 1 only solves the uncoupled blocks of its last
     // level (reassembly is the identity on the in-place layout).
-    add_launches(p, p->back, maxlev,
-                 [&](int s, int l) -> int64_t {
-                     if (!has(s, l))
-                         return 0;
-                     if (p->sched == CRSOLVE_SCHED_PCR && l + 1 != (int)lv[s].size())
-                         return 0;
-                     return lv[s][l].ne;
-                 },
-                 seg_of);
-    // gradient launches: one work item per block row of each system
-    add_launches(p, p->grad, 1, [&](int s, int) -> int64_t { return p->N[s]; },
-                 [&](int s, int) {
-                     Seg g;
-                     std::memset(&g, 0, sizeof(g));
-                     g.n = p->N[s];
-                     g.m = p->m[s];
-                     g.k = p->k[s];
-                     g.sys = s;
-                     g.oA = p->offA[s];
-                     g.oB = p->offB[s];
-                     g.oy = p->offy[s];
-                     g.ox = p->offy[s];
-                     return g;
-                 });
-    p->off_segs = off;
-    off = align_up(off + sizeof(Seg) * p->segs.size());
-    p->ws_bytes = off;
+    add_launches(p, p->back, maxlev, [&](int s, int l) -> int64_t {
+        if (p->sched == CRSOLVE_SCHED_PCR && l + 1 != (int)p->lv[s].size())
+            return 0;
+        return p->lv[s][l].ne;
+    });
+
+    // whole-system segments: gradients or residuals (one work item per block
+    // row) and norms (one per system)
+    std::vector<int64_t> rowbase(p->batch, 0);
+    for (int s = 1; s < p->batch; ++s)
+        rowbase[s] = rowbase[s - 1] + p->N[s - 1];
+    auto sys_seg = [&](int s) {
+        Seg g;
+        std::memset(&g, 0, sizeof(g));
+        g.n = p->N[s];
+        g.m = p->m[s];
+        g.k = p->k[s];
+        g.sys = s;
+        g.oA = p->offA[s];
+        g.oB = p->offB[s];
+        g.oy = p->offy[s];
+        g.ox = p->offy[s];
+        g.ob0 = rowbase[s];
+        return g;
+    };
+    for (int f = 0; f < 2; ++f)
+        for (int c = 0; c < kNumCls; ++c) {
+            // gradients: one launch per class in the plan's dtype; residuals
+            // (refine): one per class and level-0 precision
+            Launch L{0, c, f, (int)p->segs.size(), 0, 0, false, false, false};
+            for (int s = 0; s < p->batch; ++s) {
+                if (p->cls[s] != c || (f == 1) != (p->lv[s][0].f64 == 1))
+                    continue;
+                Seg g = sys_seg(s);
+                if (refine)
+                    g.og = p->lv[s][0].oy; // r lands where level 0 reads its rhs
+                g.w0 = L.total;
+                L.total += p->N[s];
+                p->segs.push_back(g);
+                ++L.nseg;
+            }
+            if (L.nseg) {
+                if (refine)
+                    p->resid.push_back(L);
+                else
+                    p->grad.push_back(L);
+            } else {
+                p->segs.resize(L.seg0);
+            }
+        }
+    p->norm_seg0 = (int)p->segs.size();
+    for (int s = 0; s < p->batch; ++s)
+        p->segs.push_back(sys_seg(s));
+
+    // conversion jobs (refine)
+    p->cvt_factor0.clear();
+    p->cvt_solve0.clear();
+    p->cvt_factor_sw.assign(maxlev + 1, {});
+    p->cvt_solve_sw.assign(maxlev + 1, {});
+    p->scatter_sw.assign(maxlev + 1, {});
+    if (refine) {
+        std::vector<JobIn> jA, jB, jy32, jy64;
+        for (int s = 0; s < p->batch; ++s) {
+            const int64_t mm = (int64_t)p->m[s] * p->m[s], mk = (int64_t)p->m[s] * p->k[s];
+            if (!p->lv[s][0].f64) {
+                jA.push_back({p->offA[s], oA32[s], (int64_t)p->N[s] * mm});
+                jB.push_back({p->offB[s], oB32[s], (int64_t)(p->N[s] - 1) * mm});
+                jy32.push_back({p->offy[s], or32[s], (int64_t)p->N[s] * mk});
+            } else {
+                jy64.push_back({p->offy[s], or64[s], (int64_t)p->N[s] * mk});
+            }
+        }
+        add_cvt(p, p->cvt_factor0, jA, 1, 0, true, 0);
+        add_cvt(p, p->cvt_factor0, jB, 1, 0, true, 1);
+        add_cvt(p, p->cvt_solve0, jy32, 1, 0, true, 2);
+        add_cvt(p, p->cvt_solve0, jy64, 1, 1, true, 2);
+        for (int l = 1; l <= maxlev; ++l) {
+            std::vector<JobIn> fa, fbv, fy;
+            for (int s = 0; s < p->batch; ++s) {
+                if (p->sw[s] != l)
+                    continue;
+                const int64_t mm = (int64_t)p->m[s] * p->m[s], mk = (int64_t)p->m[s] * p->k[s];
+                const LevelSpec &pv = p->lv[s][l - 1], &cv = p->lv[s][l];
+                // source offsets count FP32 elements, destination offsets FP64
+                // elements, both from the start of the workspace
+                fa.push_back({pv.oAo, cv.oA, (int64_t)cv.n * mm});
+                fbv.push_back({pv.oBo, cv.oB, (int64_t)std::max(cv.n - 1, 0) * mm});
+                fy.push_back({pv.oyo, cv.oy, (int64_t)cv.n * mk});
+            }
+            add_cvt(p, p->cvt_factor_sw[l], fa, 0, 1, false, 0);
+            add_cvt(p, p->cvt_factor_sw[l], fbv, 0, 1, false, 1);
+            add_cvt(p, p->cvt_solve_sw[l], fy, 0, 1, false, 2);
+        }
+        for (int l = 0; l <= maxlev; ++l) {
+            std::vector<JobIn> sc;
+            for (int s = 0; s < p->batch; ++s) {
+                if (p->sw[s] != l)
+                    continue;
+                const int64_t mk = (int64_t)p->m[s] * p->k[s];
+                const int64_t d0 = (int64_t)(p->off_d32 / e32) + p->offy[s];
+                for (int j = 0; j < p->lv[s][l].n; ++j)
+                    sc.push_back({oxt[s] + j * mk, d0 + (((int64_t)(j + 1) << l) - 1) * mk, mk});
+            }
+            add_cvt(p, p->scatter_sw[l], sc, 1, 0, false, 2);
+        }
+    }
+
+    p->off_segs = a.off;
+    a.off = align_up(a.off + sizeof(Seg) * p->segs.size());
+    p->off_jobs = a.off;
+    a.off = align_up(a.off + sizeof(CvtJob) * std::max<size_t>(p->jobs.size(), 1));
+    if (refine) {
+        p->off_fb = a.off;
+        a.off = align_up(a.off + p->fb->ws_bytes);
+    }
+    p->ws_bytes = a.off;
     return CRSOLVE_OK;
 }
 
@@ -480,12 +763,11 @@ int check_ws(const crsolve_plan* p, const void* ws, size_t ws_bytes)
 
 bool aligned(const void* ptr, size_t a) { return ptr && ((uintptr_t)ptr % a) == 0; }
 
-bool any_B(const crsolve_plan* p)
+bool any_B(const crsolve_plan* p) { return p->totB > 0; }
+
+size_t io_esz(const crsolve_plan* p)
 {
-    for (int s = 0; s < p->batch; ++s)
-        if (p->N[s] > 1)
-            return true;
-    return false;
+    return (p->dtype == CRSOLVE_C128 || p->prec == CRSOLVE_PREC_FP32_REFINE) ? 16 : 8;
 }
 
 int upload(const crsolve_plan* p, char* ws, hipStream_t st)
@@ -493,53 +775,78 @@ int upload(const crsolve_plan* p, char* ws, hipStream_t st)
     if (hipMemcpyAsync(ws + p->off_segs, p->segs.data(), sizeof(Seg) * p->segs.size(),
                        hipMemcpyHostToDevice, st) != hipSuccess)
         return CRSOLVE_EHIP;
+    if (!p->jobs.empty() &&
+        hipMemcpyAsync(ws + p->off_jobs, p->jobs.data(), sizeof(CvtJob) * p->jobs.size(),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return CRSOLVE_EHIP;
     return CRSOLVE_OK;
 }
 
-int last_err()
-{
-    return hipGetLastError() == hipSuccess ? CRSOLVE_OK : CRSOLVE_EHIP;
-}
+int last_err() { return hipGetLastError() == hipSuccess ? CRSOLVE_OK : CRSOLVE_EHIP; }
 
-Ctx make_ctx(const crsolve_plan* p, void* ws, void* stream)
-{
-    Ctx c;
-    c.p = p;
-    c.ws = (char*)ws;
-    c.dsegs = (const Seg*)(c.ws + p->off_segs);
-    c.flags = (unsigned long long*)(c.ws + p->off_flags);
-    c.st = (hipStream_t)stream;
-    return c;
-}
-
-template <class T>
+// All levels downwards: matrix part (mat), right-hand side (rhs) or both.
 void levels_down(const Ctx& c, const void* A, const void* B, const void* y, int mat, int rhs)
 {
     const crsolve_plan* p = c.p;
     size_t ie = 0, ir = 0;
     for (int l = 0; l < p->nlevels; ++l) {
-        for (; ie < p->elim.size() && p->elim[ie].level == l; ++ie)
-            run_elim<T>(c, p->elim[ie], A, B, y, mat, rhs);
-        for (; ir < p->reduce.size() && p->reduce[ir].level == l; ++ir)
-            run_reduce<T>(c, p->reduce[ir], A, y, mat, rhs);
+        for (; ie < p->elim.size() && p->elim[ie].level == l; ++ie) {
+            const Launch& L = p->elim[ie];
+            if (L.f64)
+                run_elim<double>(c, L, A, B, y, mat, rhs);
+            else
+                run_elim<float>(c, L, A, B, y, mat, rhs);
+        }
+        for (; ir < p->reduce.size() && p->reduce[ir].level == l; ++ir) {
+            const Launch& L = p->reduce[ir];
+            if (L.f64)
+                run_reduce<double>(c, L, A, y, mat, rhs);
+            else
+                run_reduce<float>(c, L, A, y, mat, rhs);
+        }
+        if (l + 1 < (int)p->cvt_factor_sw.size()) {
+            if (mat)
+                for (const CvtLaunch& cl : p->cvt_factor_sw[l + 1])
+                    run_cvt(c, cl, A, B, y);
+            if (rhs)
+                for (const CvtLaunch& cl : p->cvt_solve_sw[l + 1])
+                    run_cvt(c, cl, A, B, y);
+        }
     }
 }
 
-template <class T>
+// All levels upwards.  Before the back substitution of level l (FP32), the
+// unknowns of systems whose FP64 tail starts at level l + 1 move into the
+// FP32 correction; systems that are FP64 from level 0 move theirs last.
 void levels_up(const Ctx& c, void* x)
 {
     const crsolve_plan* p = c.p;
-    for (size_t i = p->back.size(); i-- > 0;)
-        run_back<T>(c, p->back[i], x);
+    const int nsc = (int)p->scatter_sw.size();
+    int next = p->nlevels; // scatter lists of levels >= next are done
+    for (size_t i = p->back.size(); i-- > 0;) {
+        const Launch& L = p->back[i];
+        for (; next > L.level + 1; --next)
+            if (next - 1 < nsc && next - 1 > L.level)
+                for (const CvtLaunch& cl : p->scatter_sw[next - 1])
+                    run_cvt(c, cl, nullptr, nullptr, nullptr);
+        if (L.f64)
+            run_back<double>(c, L, x);
+        else
+            run_back<float>(c, L, x);
+    }
+    for (; next > 0; --next)
+        if (next - 1 < nsc)
+            for (const CvtLaunch& cl : p->scatter_sw[next - 1])
+                run_cvt(c, cl, nullptr, nullptr, nullptr);
 }
 
-void finalize(const Ctx& c, crsolve_info* info)
+void finalize(const Ctx& c, crsolve_info* info, int fb)
 {
     if (!info)
         return;
     int n = c.p->batch;
     Timed tm(c.p, KID_FINAL, c.st);
-    hipLaunchKernelGGL(k_finalize, dim3((n + 255) / 256), dim3(256), 0, c.st, c.flags, info, n);
+    hipLaunchKernelGGL(k_finalize, dim3((n + 255) / 256), dim3(256), 0, c.st, c.flags, info, n, fb);
 }
 
 void init_flags(const Ctx& c)
@@ -547,6 +854,238 @@ void init_flags(const Ctx& c)
     int n = c.p->batch;
     Timed tm(c.p, KID_FLAGS, c.st);
     hipLaunchKernelGGL(crs::k_flags_init, dim3((n + 255) / 256), dim3(256), 0, c.st, c.flags, n);
+}
+
+// --------------------------------------------------------------- mixed form
+
+void residual(const Ctx& c, const void* A, const void* B, const void* x, const void* y)
+{
+    const crsolve_plan* p = c.p;
+    double* part = (double*)(c.ws + p->off_part);
+    for (const Launch& L : p->resid) {
+        Timed tm(p, KID_RESIDUAL, c.st);
+#define CALL(MT)                                                                                   \
+    hipLaunchKernelGGL((crs::k_residual<MT>), dim3((unsigned)L.total), dim3(64), 0, c.st,          \
+                       c.dsegs + L.seg0, L.nseg, L.total, (const cx<double>*)A,                    \
+                       (const cx<double>*)B, (const cx<double>*)x, (const cx<double>*)y,           \
+                       (void*)c.ws, L.f64 ? 0 : 1, part)
+        CRS_BY_CLASS(L.cls, CALL)
+#undef CALL
+    }
+    Timed tm(p, KID_NORMS, c.st);
+    hipLaunchKernelGGL(crs::k_norms, dim3(p->batch), dim3(256), 0, c.st, c.dsegs + p->norm_seg0,
+                       p->batch, (const double*)part, (double*)(c.ws + p->off_norms));
+}
+
+void update(const Ctx& c, void* x, int assign)
+{
+    const crsolve_plan* p = c.p;
+    Timed tm(p, KID_UPDATE, c.st);
+    const unsigned g = (unsigned)std::min<int64_t>((p->toty + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(crs::k_update, dim3(g), dim3(256), 0, c.st, (cx<double>*)x,
+                       (const cx<float>*)(c.ws + p->off_d32), p->toty, assign);
+}
+
+int read_norms(const Ctx& c, std::vector<double>& h)
+{
+    h.resize(2 * c.p->batch);
+    if (hipMemcpyAsync(h.data(), c.ws + c.p->off_norms, sizeof(double) * h.size(),
+                       hipMemcpyDeviceToHost, c.st) != hipSuccess)
+        return CRSOLVE_EHIP;
+    if (hipStreamSynchronize(c.st) != hipSuccess)
+        return CRSOLVE_EHIP;
+    return CRSOLVE_OK;
+}
+
+int write_refine_info(const Ctx& c, crsolve_info* info, const std::vector<double>& tab)
+{
+    if (!info)
+        return CRSOLVE_OK;
+    double* d = (double*)(c.ws + c.p->off_info);
+    if (hipMemcpyAsync(d, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, c.st) !=
+        hipSuccess)
+        return CRSOLVE_EHIP;
+    int n = c.p->batch;
+    hipLaunchKernelGGL(k_set_refine, dim3((n + 255) / 256), dim3(256), 0, c.st, (const double*)d,
+                       info, n);
+    // the host table must outlive the copy
+    if (hipStreamSynchronize(c.st) != hipSuccess)
+        return CRSOLVE_EHIP;
+    return CRSOLVE_OK;
+}
+
+// FP32 factorization with FP64 tail; on breakdown, the FP64 plan takes over.
+int factor_refine(const crsolve_plan* p, const void* A, const void* B, char* ws,
+                  crsolve_info* info, hipStream_t st)
+{
+    Ctx c = make_ctx(p, ws, st);
+    int rc = upload(p, ws, st);
+    if (rc)
+        return rc;
+    for (const CvtLaunch& cl : p->cvt_factor0)
+        run_cvt(c, cl, A, B, nullptr);
+    init_flags(c);
+    levels_down(c, A, B, nullptr, 1, 0);
+    std::vector<unsigned long long> fl(p->batch);
+    if (hipMemcpyAsync(fl.data(), c.flags, sizeof(unsigned long long) * p->batch,
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return CRSOLVE_EHIP;
+    bool failed = false;
+    for (unsigned long long f : fl)
+        failed |= f != crs::kNoFail;
+    p->use_fb = failed;
+    if (!failed) {
+        finalize(c, info, 0);
+        return last_err();
+    }
+    const crsolve_plan* q = p->fb.get();
+    Ctx cf = make_ctx(q, ws + p->off_fb, st);
+    if ((rc = upload(q, cf.ws, st)))
+        return rc;
+    init_flags(cf);
+    levels_down(cf, A, B, nullptr, 1, 0);
+    finalize(cf, info, 1);
+    return last_err();
+}
+
+int solve_refine(const crsolve_plan* p, char* ws, const void* A, const void* B, const void* y,
+                 void* x, crsolve_info* info, hipStream_t st)
+{
+    Ctx c = make_ctx(p, ws, st);
+    int rc = upload(p, ws, st);
+    if (rc)
+        return rc;
+    std::vector<double> nh, tab(2 * p->batch, 0.0);
+    if (p->use_fb) {
+        // FP64 factors: one solve, then the residual for the record
+        const crsolve_plan* q = p->fb.get();
+        Ctx cf = make_ctx(q, ws + p->off_fb, st);
+        if ((rc = upload(q, cf.ws, st)))
+            return rc;
+        levels_down(cf, nullptr, nullptr, y, 0, 1);
+        levels_up(cf, x);
+        residual(c, A, B, x, y);
+        if ((rc = read_norms(c, nh)))
+            return rc;
+        for (int s = 0; s < p->batch; ++s)
+            tab[2 * s + 1] = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
+        if ((rc = write_refine_info(c, info, tab)))
+            return rc;
+        return last_err();
+    }
+    // x_0 = A^{-1} y with the mixed factors
+    for (const CvtLaunch& cl : p->cvt_solve0)
+        run_cvt(c, cl, nullptr, nullptr, y);
+    levels_down(c, nullptr, nullptr, nullptr, 0, 1);
+    levels_up(c, x);
+    update(c, x, 1);
+    int it = 0;
+    for (;;) {
+        residual(c, A, B, x, y);
+        if ((rc = read_norms(c, nh)))
+            return rc;
+        bool done = true;
+        for (int s = 0; s < p->batch; ++s) {
+            const double rel = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
+            tab[2 * s] = it;
+            tab[2 * s + 1] = rel;
+            if (!(rel <= p->rtol))
+                done = false;
+        }
+        if (done || it >= p->max_refine)
+            break;
+        // d = A^{-1} r with the mixed factors (r was written where level 0
+        // reads its right-hand side), x += d
+        levels_down(c, nullptr, nullptr, nullptr, 0, 1);
+        levels_up(c, x);
+        update(c, x, 0);
+        ++it;
+    }
+    if ((rc = write_refine_info(c, info, tab)))
+        return rc;
+    return last_err();
+}
+
+int validate(const crsolve_desc* d)
+{
+    if (!d || d->batch < 1 || !d->N || !d->m || !d->k)
+        return CRSOLVE_EINVAL;
+    if (d->dtype != CRSOLVE_C128 && d->dtype != CRSOLVE_C64)
+        return CRSOLVE_EINVAL;
+    if (d->precision != CRSOLVE_PREC_NATIVE && d->precision != CRSOLVE_PREC_FP32_REFINE)
+        return CRSOLVE_EINVAL;
+    if (d->schedule != CRSOLVE_SCHED_CR && d->schedule != CRSOLVE_SCHED_PCR)
+        return CRSOLVE_EINVAL;
+    if (d->precision == CRSOLVE_PREC_FP32_REFINE &&
+        (d->dtype != CRSOLVE_C128 || d->schedule != CRSOLVE_SCHED_CR))
+        return CRSOLVE_EUNSUPPORTED;
+    if (d->precision == CRSOLVE_PREC_FP32_REFINE && (d->max_refine < 0 || !(d->rtol >= 0)))
+        return CRSOLVE_EINVAL;
+    if (d->schedule == CRSOLVE_SCHED_PCR &&
+        (d->dtype != CRSOLVE_C128 || d->precision != CRSOLVE_PREC_NATIVE))
+        return CRSOLVE_EUNSUPPORTED;
+    for (int s = 0; s < d->batch; ++s) {
+        if (d->N[s] < 1 || d->m[s] < 1 || d->k[s] < 1)
+            return CRSOLVE_EINVAL;
+        if (d->m[s] > 64)
+            return CRSOLVE_EUNSUPPORTED;
+        if ((int64_t)d->N[s] >= (1ll << 30))
+            return CRSOLVE_EUNSUPPORTED;
+    }
+    return CRSOLVE_OK;
+}
+
+crsolve_plan* new_plan(const crsolve_desc* d, crsolve_precision prec, int* rc)
+{
+    crsolve_plan* p = new (std::nothrow) crsolve_plan();
+    if (!p) {
+        *rc = CRSOLVE_EINVAL;
+        return nullptr;
+    }
+    p->batch = d->batch;
+    p->N.assign(d->N, d->N + d->batch);
+    p->m.assign(d->m, d->m + d->batch);
+    p->k.assign(d->k, d->k + d->batch);
+    p->dtype = d->dtype;
+    p->prec = prec;
+    p->sched = d->schedule;
+    p->rtol = d->rtol;
+    p->max_refine = d->max_refine;
+    p->tail = d->fp64_tail_blocks;
+    p->cls.resize(p->batch);
+    int64_t oa = 0, ob = 0, oy = 0, on = 0;
+    for (int s = 0; s < p->batch; ++s) {
+        p->cls[s] = cls_of(p->m[s]);
+        p->offA.push_back(oa);
+        p->offB.push_back(ob);
+        p->offy.push_back(oy);
+        oa += (int64_t)p->N[s] * p->m[s] * p->m[s];
+        ob += (int64_t)(p->N[s] - 1) * p->m[s] * p->m[s];
+        oy += (int64_t)p->N[s] * p->m[s] * p->k[s];
+        on += p->N[s];
+    }
+    p->totA = oa;
+    p->totB = ob;
+    p->toty = oy;
+    p->totN = on;
+    if (prec == CRSOLVE_PREC_FP32_REFINE) {
+        crsolve_desc dn = *d;
+        dn.precision = CRSOLVE_PREC_NATIVE;
+        dn.dtype = CRSOLVE_C128;
+        p->fb.reset(new_plan(&dn, CRSOLVE_PREC_NATIVE, rc));
+        if (!p->fb) {
+            delete p;
+            return nullptr;
+        }
+        p->fb->timing_parent = p;
+    }
+    *rc = build_plan(p);
+    if (*rc != CRSOLVE_OK) {
+        delete p;
+        return nullptr;
+    }
+    return p;
 }
 
 } // namespace
@@ -557,57 +1096,14 @@ extern "C" {
 
 int crsolve_plan_create(const crsolve_desc* d, crsolve_plan** out)
 {
-    if (!d || !out || d->batch < 1 || !d->N || !d->m || !d->k)
+    if (!out)
         return CRSOLVE_EINVAL;
-    if (d->dtype != CRSOLVE_C128 && d->dtype != CRSOLVE_C64)
-        return CRSOLVE_EINVAL;
-    if (d->precision != CRSOLVE_PREC_NATIVE && d->precision != CRSOLVE_PREC_FP32_REFINE)
-        return CRSOLVE_EINVAL;
-    if (d->schedule != CRSOLVE_SCHED_CR && d->schedule != CRSOLVE_SCHED_PCR)
-        return CRSOLVE_EINVAL;
-    if (d->precision == CRSOLVE_PREC_FP32_REFINE)
-        return CRSOLVE_EUNSUPPORTED;
-    if (d->schedule == CRSOLVE_SCHED_PCR &&
-        (d->dtype != CRSOLVE_C128 || d->precision != CRSOLVE_PREC_NATIVE))
-        return CRSOLVE_EUNSUPPORTED;
-    for (int s = 0; s < d->batch; ++s) {
-        if (d->N[s] < 1 || d->m[s] < 1 || d->k[s] < 1)
-            return CRSOLVE_EINVAL;
-        if (d->m[s] > 64)
-            return CRSOLVE_EUNSUPPORTED;
-        if ((int64_t)d->N[s] >= (1ll << 31) / 2)
-            return CRSOLVE_EUNSUPPORTED;
-    }
-    crsolve_plan* p = new (std::nothrow) crsolve_plan();
-    if (!p)
-        return CRSOLVE_EINVAL;
-    p->batch = d->batch;
-    p->N.assign(d->N, d->N + d->batch);
-    p->m.assign(d->m, d->m + d->batch);
-    p->k.assign(d->k, d->k + d->batch);
-    p->dtype = d->dtype;
-    p->prec = d->precision;
-    p->sched = d->schedule;
-    p->rtol = d->rtol;
-    p->max_refine = d->max_refine;
-    p->tail = d->fp64_tail_blocks;
-    p->esz = d->dtype == CRSOLVE_C128 ? 16 : 8;
-    p->cls.resize(p->batch);
-    int64_t oa = 0, ob = 0, oy = 0;
-    for (int s = 0; s < p->batch; ++s) {
-        p->cls[s] = cls_of(p->m[s]);
-        p->offA.push_back(oa);
-        p->offB.push_back(ob);
-        p->offy.push_back(oy);
-        oa += (int64_t)p->N[s] * p->m[s] * p->m[s];
-        ob += (int64_t)(p->N[s] - 1) * p->m[s] * p->m[s];
-        oy += (int64_t)p->N[s] * p->m[s] * p->k[s];
-    }
-    int rc = build_plan(p);
-    if (rc != CRSOLVE_OK) {
-        delete p;
+    int rc = validate(d);
+    if (rc)
         return rc;
-    }
+    crsolve_plan* p = new_plan(d, d->precision, &rc);
+    if (!p)
+        return rc ? rc : CRSOLVE_EINVAL;
     *out = p;
     return CRSOLVE_OK;
 }
@@ -691,26 +1187,22 @@ int crsolve_factor(crsolve_plan* p, const void* A, const void* B, void* ws, size
     int rc = check_ws(p, ws, ws_bytes);
     if (rc)
         return rc;
-    if (!aligned(A, p->esz) || (any_B(p) && !aligned(B, p->esz)))
+    if (!aligned(A, io_esz(p)) || (any_B(p) && !aligned(B, io_esz(p))))
         return CRSOLVE_EINVAL;
+    if (p->prec == CRSOLVE_PREC_FP32_REFINE)
+        return factor_refine(p, A, B, (char*)ws, info, (hipStream_t)stream);
     Ctx c = make_ctx(p, ws, stream);
     if ((rc = upload(p, c.ws, c.st)))
         return rc;
     init_flags(c);
-    if (p->dtype == CRSOLVE_C128)
-        levels_down<double>(c, A, B, nullptr, 1, 0);
-    else
-        levels_down<float>(c, A, B, nullptr, 1, 0);
-    finalize(c, info);
+    levels_down(c, A, B, nullptr, 1, 0);
+    finalize(c, info, 0);
     return last_err();
 }
 
 int crsolve_solve(const crsolve_plan* p, void* ws, size_t ws_bytes, const void* A, const void* B,
                   const void* y, void* x, crsolve_info* info, void* stream)
 {
-    (void)A;
-    (void)B;
-    (void)info;
     if (!p)
         return CRSOLVE_EINVAL;
     if (p->sched != CRSOLVE_SCHED_CR)
@@ -718,18 +1210,18 @@ int crsolve_solve(const crsolve_plan* p, void* ws, size_t ws_bytes, const void* 
     int rc = check_ws(p, ws, ws_bytes);
     if (rc)
         return rc;
-    if (!aligned(y, p->esz) || !aligned(x, p->esz))
+    if (!aligned(y, io_esz(p)) || !aligned(x, io_esz(p)))
         return CRSOLVE_EINVAL;
+    if (p->prec == CRSOLVE_PREC_FP32_REFINE) {
+        if (!aligned(A, 16) || (any_B(p) && !aligned(B, 16)))
+            return CRSOLVE_EINVAL;
+        return solve_refine(p, (char*)ws, A, B, y, x, info, (hipStream_t)stream);
+    }
     Ctx c = make_ctx(p, ws, stream);
     if ((rc = upload(p, c.ws, c.st)))
         return rc;
-    if (p->dtype == CRSOLVE_C128) {
-        levels_down<double>(c, nullptr, nullptr, y, 0, 1);
-        levels_up<double>(c, x);
-    } else {
-        levels_down<float>(c, nullptr, nullptr, y, 0, 1);
-        levels_up<float>(c, x);
-    }
+    levels_down(c, nullptr, nullptr, y, 0, 1);
+    levels_up(c, x);
     return last_err();
 }
 
@@ -741,21 +1233,21 @@ int crsolve_factor_solve(crsolve_plan* p, const void* A, const void* B, const vo
     int rc = check_ws(p, ws, ws_bytes);
     if (rc)
         return rc;
-    if (!aligned(A, p->esz) || (any_B(p) && !aligned(B, p->esz)) || !aligned(y, p->esz) ||
-        !aligned(x, p->esz))
+    const size_t es = io_esz(p);
+    if (!aligned(A, es) || (any_B(p) && !aligned(B, es)) || !aligned(y, es) || !aligned(x, es))
         return CRSOLVE_EINVAL;
+    if (p->prec == CRSOLVE_PREC_FP32_REFINE) {
+        if ((rc = factor_refine(p, A, B, (char*)ws, info, (hipStream_t)stream)))
+            return rc;
+        return solve_refine(p, (char*)ws, A, B, y, x, info, (hipStream_t)stream);
+    }
     Ctx c = make_ctx(p, ws, stream);
     if ((rc = upload(p, c.ws, c.st)))
         return rc;
     init_flags(c);
-    if (p->dtype == CRSOLVE_C128) {
-        levels_down<double>(c, A, B, y, 1, 1);
-        levels_up<double>(c, x);
-    } else {
-        levels_down<float>(c, A, B, y, 1, 1);
-        levels_up<float>(c, x);
-    }
-    finalize(c, info);
+    levels_down(c, A, B, y, 1, 1);
+    levels_up(c, x);
+    finalize(c, info, 0);
     return last_err();
 }
 
@@ -769,22 +1261,20 @@ int crsolve_backward(const crsolve_plan* p, void* ws, size_t ws_bytes, const voi
     int rc = check_ws(p, ws, ws_bytes);
     if (rc)
         return rc;
-    if (!aligned(x, p->esz) || !aligned(grad_x, p->esz) || !aligned(grad_y, p->esz) ||
-        !aligned(grad_A, p->esz) || (any_B(p) && !aligned(grad_B, p->esz)))
+    const size_t es = io_esz(p);
+    if (!aligned(x, es) || !aligned(grad_x, es) || !aligned(grad_y, es) || !aligned(grad_A, es) ||
+        (any_B(p) && !aligned(grad_B, es)))
         return CRSOLVE_EINVAL;
     Ctx c = make_ctx(p, ws, stream);
     if ((rc = upload(p, c.ws, c.st)))
         return rc;
     // lam = A^{-1} grad_x with the stored factors, written straight into grad_y
-    if (p->dtype == CRSOLVE_C128) {
-        levels_down<double>(c, nullptr, nullptr, grad_x, 0, 1);
-        levels_up<double>(c, grad_y);
-        for (const Launch& L : p->grad)
+    levels_down(c, nullptr, nullptr, grad_x, 0, 1);
+    levels_up(c, grad_y);
+    for (const Launch& L : p->grad) {
+        if (L.f64)
             run_grad<double>(c, L, x, grad_y, grad_A, grad_B);
-    } else {
-        levels_down<float>(c, nullptr, nullptr, grad_x, 0, 1);
-        levels_up<float>(c, grad_y);
-        for (const Launch& L : p->grad)
+        else
             run_grad<float>(c, L, x, grad_y, grad_A, grad_B);
     }
     return last_err();

@@ -93,9 +93,13 @@ class Solver:
         self.factored = True
 
     def solve(self, y, x=None, A=None, B=None):
+        """Solve with the stored factors.  The mixed-precision form also needs
+        the FP64 matrix (A, B) for its residuals."""
         if not self.factored:
             raise RuntimeError("solve before factor")
         self._rhs(y)
+        if self.plan.precision == _lib.PREC_FP32_REFINE:
+            self._mat(A, B)
         x = self._out(x, y)
         self.plan.solve(_ptr(self.ws), _ptr(A), _ptr(B), _ptr(y), _ptr(x), _ptr(self.info),
                         _stream(self.device))
@@ -109,6 +113,13 @@ class Solver:
                                _ptr(self.info), _stream(self.device))
         self.factored = self.plan.schedule == _lib.SCHED_CR
         return x
+
+    def timing(self, enable=True):
+        """Per-kernel HIP-event timing of this solver's launches."""
+        self.plan.timing(enable)
+
+    def timing_read(self):
+        return self.plan.timing_read()
 
     def backward(self, x, gx):
         """Returns (grad_A, grad_B, grad_y) for the factored matrix."""

@@ -1,0 +1,145 @@
+"""Mixed-precision form (GPU): complex FP32 reduction levels, FP64 tail
+levels, FP64 residuals and iterative refinement to ||y - A x||_F / ||y||_F <=
+1e-12, with a fall back to FP64 when the FP32 factorization breaks down.
+Results are compared with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_00370_amd import workloads as W
+from tests._dense import dense
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def tdev(cuda_ok):
+    import torch
+    from paper_1807_00370_amd import _lib
+    _lib.load()
+    return torch, torch.device("cuda:0")
+
+
+def _run(torch, dev, systems, tail=8, max_refine=30, two_calls=False):
+    from paper_1807_00370_amd.solver import Solver
+    A = np.concatenate([s.A.ravel() for s in systems])
+    B = np.concatenate([s.B.ravel() for s in systems])
+    y = np.concatenate([s.y.ravel() for s in systems])
+    At, Bt, yt = (torch.from_numpy(v).to(dev) for v in (A, B, y))
+    sol = Solver([s.N for s in systems], [s.m for s in systems], [s.k for s in systems],
+                 precision="fp32_refine", device=dev, rtol=RTOL, max_refine=max_refine,
+                 fp64_tail_blocks=tail)
+    if two_calls:
+        sol.factor(At, Bt)
+        x = sol.solve(yt, A=At, B=Bt)
+    else:
+        x = sol.factor_solve(At, Bt, yt)
+    torch.cuda.synchronize()
+    x = x.cpu().numpy()
+    out, off = [], 0
+    for s in systems:
+        out.append(x[off:off + s.y.size].reshape(s.y.shape))
+        off += s.y.size
+    return out, sol.info_host()
+
+
+def _check(s, x, rec, tol):
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert int(rec["status"]) == io["status"] == 0
+    res = oracle.rel_residual(s.A, s.B, x, s.y)
+    assert res <= RTOL
+    assert abs(float(rec["rel_residual"]) - res) <= 0.1 * res + 1e-16
+    err = np.abs(x - xo).max() / np.abs(xo).max()
+    assert err <= tol, err
+    return res, err
+
+
+@pytest.mark.parametrize("N,m,k,tail", [(2000, 32, 16, 8), (777, 16, 4, 8), (300, 64, 8, 8),
+                                        (100, 8, 2, 0), (6, 4, 1, 8), (129, 32, 16, 64)])
+def test_refine_matches_fp64_oracle(tdev, N, m, k, tail):
+    torch, dev = tdev
+    print("case refine N=%d m=%d k=%d tail=%d" % (N, m, k, tail), flush=True)
+    s = W.random_hpd(N, m, k, W.config_seed(2) + N + m)
+    (x,), rec = _run(torch, dev, [s], tail=tail)
+    _check(s, x, rec[0], 1e-11)
+    assert int(rec[0]["fp64_fallback"]) == 0
+    assert int(rec[0]["refine_iters"]) <= 6
+
+
+def test_refine_factor_then_solve(tdev):
+    torch, dev = tdev
+    s = W.random_hpd(1000, 32, 16, 77)
+    (x,), rec = _run(torch, dev, [s], two_calls=True)
+    _check(s, x, rec[0], 1e-11)
+
+
+def test_refine_stated_ill_variant(tdev):
+    """The generator with margin 1 replaced by 1e-5 (||B_{j-1}|| + ||B_j||)."""
+    torch, dev = tdev
+    s = W.random_hpd(4000, 32, 16, W.config_seed(2, 1), ill=True)
+    (x,), rec = _run(torch, dev, [s])
+    _check(s, x, rec[0], 1e-10)
+
+
+def test_refine_calibrated_kappa_1e5(tdev):
+    """Shift A_j by c I so that kappa(A) = 1e5 (extreme eigenvalues from a
+    dense eigensolver on this small instance): refinement still reaches the
+    FP64 residual bound."""
+    torch, dev = tdev
+    s = W.random_hpd(96, 8, 4, 4242)
+    ev = np.linalg.eigvalsh(dense(s.A, s.B))
+    lo, hi = ev[0], ev[-1]
+    kappa = 1e5
+    c = lo - (hi - lo) / (kappa - 1)
+    A2 = s.A - c * np.eye(8)[None]
+    ev2 = np.linalg.eigvalsh(dense(A2, s.B))
+    assert abs(ev2[-1] / ev2[0] / kappa - 1) < 1e-3
+    s2 = W.System(A2, s.B, s.y)
+    (x,), rec = _run(torch, dev, [s2], tail=0, max_refine=60)
+    res = oracle.rel_residual(s2.A, s2.B, x, s2.y)
+    assert int(rec[0]["status"]) == 0 and res <= RTOL
+    xo, _ = oracle.solve_cr(s2.A, s2.B, s2.y)
+    assert np.abs(x - xo).max() / np.abs(xo).max() <= kappa * 1e-11
+
+
+def test_refine_fp32_breakdown_falls_back(tdev):
+    """B_1 = 1 - 1e-10 with A_j = 1: positive definite, but the reduced pivot
+    1 - B_1^2 rounds to 0 in FP32, so the FP32 factorization breaks down and
+    the FP64 plan takes over."""
+    torch, dev = tdev
+    N = 64
+    A = np.ones((N, 1, 1), np.complex128)
+    B = np.zeros((N - 1, 1, 1), np.complex128)
+    B[0] = 1 - 1e-10
+    y = np.arange(1, N + 1, dtype=np.complex128).reshape(N, 1, 1)
+    s = W.System(A, B, y)
+    (x,), rec = _run(torch, dev, [s], tail=0)
+    assert int(rec[0]["fp64_fallback"]) == 1
+    assert int(rec[0]["status"]) == 0
+    xo, _ = oracle.solve_cr(A, B, y)
+    res = oracle.rel_residual(A, B, x, y)
+    assert res <= RTOL
+    assert float(rec[0]["rel_residual"]) <= RTOL
+
+
+def test_refine_indefinite_reports_fp64_flag(tdev):
+    torch, dev = tdev
+    t = W.random_hpd(**W.TINY, seed=W.config_seed(0), shift_scale=2.0)
+    (x,), rec = _run(torch, dev, [t], tail=0)
+    _, io = oracle.solve_cr(t.A, t.B, t.y)
+    assert (int(rec[0]["status"]), int(rec[0]["level"]), int(rec[0]["block"])) == \
+        (io["status"], io["level"], io["block"])
+    assert int(rec[0]["fp64_fallback"]) == 1
+    assert np.isnan(x).all()
+
+
+def test_refine_ragged_batch(tdev):
+    torch, dev = tdev
+    shapes = [(256, 8, 1), (512, 16, 4), (300, 32, 16), (258, 64, 4), (6, 8, 1), (1024, 16, 16),
+              (130, 32, 1)]
+    systems = [W.random_hpd(N, m, k, 900 + i) for i, (N, m, k) in enumerate(shapes)]
+    xs, rec = _run(torch, dev, systems)
+    for s, x, r in zip(systems, xs, rec):
+        _check(s, x, r, 1e-11)
