@@ -165,6 +165,14 @@ int crsolve_factor_solve(crsolve_plan *plan, const void *A, const void *B, const
 int crsolve_backward(const crsolve_plan *plan, void *ws, size_t ws_bytes, const void *x,
                      const void *grad_x, void *grad_y, void *grad_A, void *grad_B, void *stream);
 
+/* Relative residuals ||y - A x||_F / ||y||_F of Eq. (Axb), one per system,
+ * computed in FP64 on the device (Hermitian reading of A_j, Frobenius norms
+ * over all N m k entries).  C128 inputs (NATIVE C128 or FP32_REFINE plans);
+ * the workspace must be the plan's.  Synchronizes the stream and writes
+ * rel[batch] to host memory.  EUNSUPPORTED for C64 plans. */
+int crsolve_residual(const crsolve_plan *plan, void *ws, size_t ws_bytes, const void *A,
+                     const void *B, const void *x, const void *y, double *rel, void *stream);
+
 /* Per-kernel timing, for measurement.  While enabled, every launch the plan
  * makes is bracketed by two HIP events recorded on the launch's stream (the
  * events come from a pool owned by the plan; no device memory is allocated).

@@ -21,7 +21,7 @@ SCHED_CR, SCHED_PCR = 0, 1
 OK, EINVAL, EHIP, EWORKSPACE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
 
 EXPORTS = ("crsolve_plan_create", "crsolve_workspace_size", "crsolve_factor", "crsolve_solve",
-           "crsolve_factor_solve", "crsolve_backward", "crsolve_timing_enable",
+           "crsolve_factor_solve", "crsolve_backward", "crsolve_residual", "crsolve_timing_enable",
            "crsolve_timing_read", "crsolve_plan_destroy", "crsolve_error_string")
 
 
@@ -79,6 +79,7 @@ def load():
     lib.crsolve_solve.argtypes = [P, P, S, P, P, P, P, P, P]
     lib.crsolve_factor_solve.argtypes = [P, P, P, P, P, S, P, P, P]
     lib.crsolve_backward.argtypes = [P, P, S, P, P, P, P, P, P]
+    lib.crsolve_residual.argtypes = [P, P, S, P, P, P, P, ctypes.POINTER(ctypes.c_double), P]
     lib.crsolve_timing_enable.argtypes = [P, ctypes.c_int]
     lib.crsolve_timing_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]
@@ -139,6 +140,13 @@ class Plan:
     def factor_solve(self, A, B, y, ws, x, info, stream):
         check("crsolve_factor_solve", load().crsolve_factor_solve(self._h, A, B, y, ws,
                                                                   self.ws_bytes, x, info, stream))
+
+    def residual(self, ws, A, B, x, y, stream):
+        """Per-system FP64 relative residuals (synchronizes)."""
+        out = (ctypes.c_double * self.batch)()
+        check("crsolve_residual", load().crsolve_residual(self._h, ws, self.ws_bytes, A, B, x, y,
+                                                          out, stream))
+        return [float(v) for v in out]
 
     def timing(self, enable: bool):
         check("crsolve_timing_enable", load().crsolve_timing_enable(self._h, int(enable)))

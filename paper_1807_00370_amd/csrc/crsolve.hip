@@ -481,17 +481,20 @@ int build_plan(crsolve_plan* p)
     p->sw.assign(p->batch, -1);
     const size_t e32 = sizeof(cx<float>), e64 = sizeof(cx<double>);
 
-    // refinement buffers: the correction d (complex FP32, laid out like y),
-    // residual norm partials and totals, the info table
+    // residual norm partials and totals (FP64 inputs); for refinement also
+    // the correction d (complex FP32, laid out like y) and the info table
     std::vector<int64_t> oA32(p->batch, 0), oB32(p->batch, 0), or32(p->batch, 0),
         or64(p->batch, 0), oxt(p->batch, 0);
-    if (refine) {
-        p->off_d32 = a.off;
-        a.off = align_up(a.off + (size_t)p->toty * e32);
+    const bool io64 = refine || f64native;
+    if (io64) {
         p->off_part = a.off;
         a.off = align_up(a.off + sizeof(double) * 2 * (size_t)std::max<int64_t>(p->totN, 1));
         p->off_norms = a.off;
         a.off = align_up(a.off + sizeof(double) * 2 * p->batch);
+    }
+    if (refine) {
+        p->off_d32 = a.off;
+        a.off = align_up(a.off + (size_t)p->toty * e32);
         p->off_info = a.off;
         a.off = align_up(a.off + sizeof(double) * 2 * p->batch);
     }
@@ -658,31 +661,33 @@ int build_plan(crsolve_plan* p)
         g.ob0 = rowbase[s];
         return g;
     };
-    for (int f = 0; f < 2; ++f)
-        for (int c = 0; c < kNumCls; ++c) {
-            // gradients: one launch per class in the plan's dtype; residuals
-            // (refine): one per class and level-0 precision
-            Launch L{0, c, f, (int)p->segs.size(), 0, 0, false, false, false};
-            for (int s = 0; s < p->batch; ++s) {
-                if (p->cls[s] != c || (f == 1) != (p->lv[s][0].f64 == 1))
+    for (int kind = 0; kind < 2; ++kind)
+        for (int f = 0; f < 2; ++f)
+            for (int c = 0; c < kNumCls; ++c) {
+                // kind 0, gradients: one launch per class in the plan's dtype;
+                // kind 1, residuals (FP64 inputs): one launch per class and
+                // level-0 precision
+                if (kind == 0 && refine)
                     continue;
-                Seg g = sys_seg(s);
-                if (refine)
-                    g.og = p->lv[s][0].oy; // r lands where level 0 reads its rhs
-                g.w0 = L.total;
-                L.total += p->N[s];
-                p->segs.push_back(g);
-                ++L.nseg;
-            }
-            if (L.nseg) {
-                if (refine)
-                    p->resid.push_back(L);
+                if (kind == 1 && !io64)
+                    continue;
+                Launch L{0, c, f, (int)p->segs.size(), 0, 0, false, false, false};
+                for (int s = 0; s < p->batch; ++s) {
+                    if (p->cls[s] != c || (f == 1) != (p->lv[s][0].f64 == 1))
+                        continue;
+                    Seg g = sys_seg(s);
+                    if (refine)
+                        g.og = p->lv[s][0].oy; // r lands where level 0 reads its rhs
+                    g.w0 = L.total;
+                    L.total += p->N[s];
+                    p->segs.push_back(g);
+                    ++L.nseg;
+                }
+                if (L.nseg)
+                    (kind == 0 ? p->grad : p->resid).push_back(L);
                 else
-                    p->grad.push_back(L);
-            } else {
-                p->segs.resize(L.seg0);
+                    p->segs.resize(L.seg0);
             }
-        }
     p->norm_seg0 = (int)p->segs.size();
     for (int s = 0; s < p->batch; ++s)
         p->segs.push_back(sys_seg(s));
@@ -858,17 +863,19 @@ void init_flags(const Ctx& c)
 
 // --------------------------------------------------------------- mixed form
 
-void residual(const Ctx& c, const void* A, const void* B, const void* x, const void* y)
+void residual(const Ctx& c, const void* A, const void* B, const void* x, const void* y,
+              bool store_r)
 {
     const crsolve_plan* p = c.p;
     double* part = (double*)(c.ws + p->off_part);
+    void* R = store_r ? (void*)c.ws : nullptr;
     for (const Launch& L : p->resid) {
         Timed tm(p, KID_RESIDUAL, c.st);
 #define CALL(MT)                                                                                   \
     hipLaunchKernelGGL((crs::k_residual<MT>), dim3((unsigned)L.total), dim3(64), 0, c.st,          \
                        c.dsegs + L.seg0, L.nseg, L.total, (const cx<double>*)A,                    \
-                       (const cx<double>*)B, (const cx<double>*)x, (const cx<double>*)y,           \
-                       (void*)c.ws, L.f64 ? 0 : 1, part)
+                       (const cx<double>*)B, (const cx<double>*)x, (const cx<double>*)y, R,        \
+                       L.f64 ? 0 : 1, part)
         CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
     }
@@ -965,7 +972,7 @@ int solve_refine(const crsolve_plan* p, char* ws, const void* A, const void* B, 
             return rc;
         levels_down(cf, nullptr, nullptr, y, 0, 1);
         levels_up(cf, x);
-        residual(c, A, B, x, y);
+        residual(c, A, B, x, y, false);
         if ((rc = read_norms(c, nh)))
             return rc;
         for (int s = 0; s < p->batch; ++s)
@@ -982,7 +989,7 @@ int solve_refine(const crsolve_plan* p, char* ws, const void* A, const void* B, 
     update(c, x, 1);
     int it = 0;
     for (;;) {
-        residual(c, A, B, x, y);
+        residual(c, A, B, x, y, true);
         if ((rc = read_norms(c, nh)))
             return rc;
         bool done = true;
@@ -1156,6 +1163,30 @@ int crsolve_timing_read(crsolve_plan* p, crsolve_kernel_time* out, int cap, int*
     }
     *n = j;
     return CRSOLVE_OK;
+}
+
+int crsolve_residual(const crsolve_plan* p, void* ws, size_t ws_bytes, const void* A,
+                     const void* B, const void* x, const void* y, double* rel, void* stream)
+{
+    if (!p || !rel)
+        return CRSOLVE_EINVAL;
+    if (p->resid.empty())
+        return CRSOLVE_EUNSUPPORTED;
+    int rc = check_ws(p, ws, ws_bytes);
+    if (rc)
+        return rc;
+    if (!aligned(A, 16) || (any_B(p) && !aligned(B, 16)) || !aligned(x, 16) || !aligned(y, 16))
+        return CRSOLVE_EINVAL;
+    Ctx c = make_ctx(p, ws, stream);
+    if ((rc = upload(p, c.ws, c.st)))
+        return rc;
+    residual(c, A, B, x, y, false);
+    std::vector<double> nh;
+    if ((rc = read_norms(c, nh)))
+        return rc;
+    for (int s = 0; s < p->batch; ++s)
+        rel[s] = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
+    return last_err();
 }
 
 int crsolve_plan_destroy(crsolve_plan* p)

@@ -83,7 +83,8 @@ __device__ __forceinline__ double wave_sum(double v)
 // into the caller's FP64 arrays, og the offset of r in R, ob0 the first row
 // of the system in the norm partials):
 //   r_j = y_j - B_{j-1} x_{j-1} - A_j x_j - B_j^H x_{j+1}
-// stored in R as FP32 (r_f32) or FP64; part[2 (ob0 + j)] = ||r_j||_F^2 and
+// stored in R (unless R is null) as FP32 (r_f32) or FP64;
+// part[2 (ob0 + j)] = ||r_j||_F^2 and
 // part[2 (ob0 + j) + 1] = ||y_j||_F^2.
 template <int MT>
 __global__ __launch_bounds__(64, 2) void k_residual(const Seg* __restrict__ segs, int nseg,
@@ -131,6 +132,8 @@ __global__ __launch_bounds__(64, 2) void k_residual(const Seg* __restrict__ segs
                     const cx<T> r{y.r - cr[u], y.i - ci[u]};
                     sr += r.r * r.r + r.i * r.i;
                     sy += y.r * y.r + y.i * y.i;
+                    if (!R)
+                        continue;
                     if (r_f32)
                         ((cx<float>*)R)[s.og + j * mk + i * k + c] = cx<float>{(float)r.r, (float)r.i};
                     else

@@ -114,6 +114,15 @@ class Solver:
         self.factored = self.plan.schedule == _lib.SCHED_CR
         return x
 
+    def residual(self, A, B, x, y):
+        """FP64 relative residuals ||y - A x||_F / ||y||_F per system, computed
+        by the library on the device (synchronizes)."""
+        self._mat(A, B)
+        self._rhs(x, "x")
+        self._rhs(y)
+        return self.plan.residual(_ptr(self.ws), _ptr(A), _ptr(B), _ptr(x), _ptr(y),
+                                  _stream(self.device))
+
     def timing(self, enable=True):
         """Per-kernel HIP-event timing of this solver's launches."""
         self.plan.timing(enable)

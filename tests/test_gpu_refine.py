@@ -143,3 +143,25 @@ def test_refine_ragged_batch(tdev):
     xs, rec = _run(torch, dev, systems)
     for s, x, r in zip(systems, xs, rec):
         _check(s, x, r, 1e-11)
+
+
+def test_library_residual_matches_oracle(tdev):
+    """crsolve_residual (FP64 on the device) equals the oracle's residual."""
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import Solver
+    shapes = [(300, 32, 16), (129, 8, 1), (64, 64, 4)]
+    systems = [W.random_hpd(N, m, k, 1300 + i) for i, (N, m, k) in enumerate(shapes)]
+    A = np.concatenate([s.A.ravel() for s in systems])
+    B = np.concatenate([s.B.ravel() for s in systems])
+    y = np.concatenate([s.y.ravel() for s in systems])
+    rng = np.random.default_rng(5)
+    xs = [s.y * 0.3 + 0.01 * (rng.standard_normal(s.y.shape) + 1j * rng.standard_normal(s.y.shape))
+          for s in systems]
+    x = np.concatenate([v.ravel() for v in xs])
+    sol = Solver([s.N for s in systems], [s.m for s in systems], [s.k for s in systems],
+                 device=dev)
+    At, Bt, yt, xt = (torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (A, B, y, x))
+    rel = sol.residual(At, Bt, xt, yt)
+    for s, xv, r in zip(systems, xs, rel):
+        ro = oracle.rel_residual(s.A, s.B, xv, s.y)
+        assert abs(r - ro) <= 1e-12 * ro
