@@ -161,7 +161,32 @@ def time_form(torch, sol, A, B, y, x, steps, warmup):
     return ms, {kn: (cnt / steps, tot / steps) for kn, (cnt, tot) in kt.items()}
 
 
-def roofline(per_step, mod, prec_f64):
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1807_00370_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(form, kernel):
+    """HBM bytes per launch from the committed counter summary of this
+    workload, or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s_N65536_m32_k16.json" % form)
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes_per_launch"]
+
+
+def roofline(per_step, mod, prec_f64, form="fp64"):
     timed = [kn for kn in mod if kn in per_step]
     dom = max(timed, key=lambda kn: per_step[kn][1])
     launches, kms = per_step[dom]
@@ -175,7 +200,7 @@ def roofline(per_step, mod, prec_f64):
         ach = flops / launches / (avg_ms * 1e-3) / 1e12
         r = {"bound": "mfma", "achieved": ach, "peak": peak_f, "unit": "TFLOP/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = None
+    r["traffic"] = measured_traffic(form, dom)
     r["kernel"] = dom
     r["avg_launch_ms"] = avg_ms
     r["launches_per_step"] = launches
@@ -195,6 +220,9 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32_refine")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="one plain device copy of A (known size) before timing, to calibrate "
+                         "HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs each system on a single "
@@ -215,6 +243,13 @@ def main():
     B = torch.from_numpy(s.B).to(dev)
     y = torch.from_numpy(s.y).to(dev)
     x = torch.empty_like(y)
+    if args.calib_copy:
+        dst = torch.empty_like(A)
+        dst.copy_(A)
+        torch.cuda.synchronize()
+        print("calibration copy: %d bytes read, %d bytes written" % (A.numel() * 16, A.numel() * 16),
+              file=sys.stderr, flush=True)
+        del dst
 
     forms = {}
     for form in args.forms.split(","):
@@ -239,7 +274,7 @@ def main():
             "fp64_fallback": int(info["fp64_fallback"]) if form != "fp64" else 0,
             "kernel_ms_per_step": {kn: round(v[1], 4) for kn, v in per_step.items()},
             "kernel_launches_per_step": {kn: v[0] for kn, v in per_step.items()},
-            "roofline": roofline(per_step, mod, form == "fp64"),
+            "roofline": roofline(per_step, mod, form == "fp64", form),
             "model_bytes": sum(v[0] for v in mod.values()),
             "model_flops": sum(v[1] for v in mod.values()),
         }
