@@ -173,6 +173,27 @@ int crsolve_backward(const crsolve_plan *plan, void *ws, size_t ws_bytes, const 
 int crsolve_residual(const crsolve_plan *plan, void *ws, size_t ws_bytes, const void *A,
                      const void *B, const void *x, const void *y, double *rel, void *stream);
 
+/* HIP graphs.  With graphs enabled, crsolve_factor_solve (NATIVE plans) and
+ * the factor part and each solve/correction pass of FP32_REFINE plans are
+ * recorded once per distinct set of pointers (A, B, y, x, ws, info) into a
+ * HIP graph on a plan-owned capture stream and afterwards replayed on the
+ * caller's stream (one graph launch instead of one launch per level and
+ * kernel).  A recorded graph binds the workspace: it must not be used by
+ * another plan or for other data while the plan lives.  The graphs contain
+ * kernel nodes only.  enable = 0 releases the recorded graphs. */
+int crsolve_set_graphs(crsolve_plan *plan, int enable);
+
+/* Autotuner.  For every (block-size class, precision) present in the plan it
+ * times, on the given data, the two kernel variants of each level role --
+ * one-wave/MFMA kernels and work-group kernels -- for the elimination, the
+ * reduced-system formation and the back substitution, and keeps the faster
+ * one (synchronizes; overwrites x and the workspace).  The choice is returned
+ * as a short text (cap bytes, NUL-terminated) that crsolve_set_tuning applies
+ * to another plan, e.g. from a cache file.  NATIVE plans only. */
+int crsolve_autotune(crsolve_plan *plan, const void *A, const void *B, const void *y, void *ws,
+                     size_t ws_bytes, void *x, void *stream, char *choice, size_t cap);
+int crsolve_set_tuning(crsolve_plan *plan, const char *choice);
+
 /* Per-kernel timing, for measurement.  While enabled, every launch the plan
  * makes is bracketed by two HIP events recorded on the launch's stream (the
  * events come from a pool owned by the plan; no device memory is allocated).

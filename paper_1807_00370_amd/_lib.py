@@ -21,7 +21,8 @@ SCHED_CR, SCHED_PCR = 0, 1
 OK, EINVAL, EHIP, EWORKSPACE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
 
 EXPORTS = ("crsolve_plan_create", "crsolve_workspace_size", "crsolve_factor", "crsolve_solve",
-           "crsolve_factor_solve", "crsolve_backward", "crsolve_residual", "crsolve_timing_enable",
+           "crsolve_factor_solve", "crsolve_backward", "crsolve_residual", "crsolve_set_graphs",
+           "crsolve_autotune", "crsolve_set_tuning", "crsolve_timing_enable",
            "crsolve_timing_read", "crsolve_plan_destroy", "crsolve_error_string")
 
 
@@ -80,6 +81,9 @@ def load():
     lib.crsolve_factor_solve.argtypes = [P, P, P, P, P, S, P, P, P]
     lib.crsolve_backward.argtypes = [P, P, S, P, P, P, P, P, P]
     lib.crsolve_residual.argtypes = [P, P, S, P, P, P, P, ctypes.POINTER(ctypes.c_double), P]
+    lib.crsolve_set_graphs.argtypes = [P, ctypes.c_int]
+    lib.crsolve_autotune.argtypes = [P, P, P, P, P, S, P, P, ctypes.c_char_p, S]
+    lib.crsolve_set_tuning.argtypes = [P, ctypes.c_char_p]
     lib.crsolve_timing_enable.argtypes = [P, ctypes.c_int]
     lib.crsolve_timing_read.argtypes = [P, ctypes.POINTER(KernelTime), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]
@@ -147,6 +151,18 @@ class Plan:
         check("crsolve_residual", load().crsolve_residual(self._h, ws, self.ws_bytes, A, B, x, y,
                                                           out, stream))
         return [float(v) for v in out]
+
+    def set_graphs(self, enable: bool):
+        check("crsolve_set_graphs", load().crsolve_set_graphs(self._h, int(enable)))
+
+    def autotune(self, A, B, y, ws, x, stream) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        check("crsolve_autotune", load().crsolve_autotune(self._h, A, B, y, ws, self.ws_bytes, x,
+                                                          stream, buf, 4096))
+        return buf.value.decode()
+
+    def set_tuning(self, choice: str):
+        check("crsolve_set_tuning", load().crsolve_set_tuning(self._h, choice.encode()))
 
     def timing(self, enable: bool):
         check("crsolve_timing_enable", load().crsolve_timing_enable(self._h, int(enable)))

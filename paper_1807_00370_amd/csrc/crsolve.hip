@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <string>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -141,6 +143,19 @@ struct crsolve_plan {
     std::unique_ptr<crsolve_plan> fb; // FP64 plan used after an FP32 breakdown
     mutable bool use_fb = false;
 
+    // kernel variant per (role: elim, reduce, back; class; precision):
+    // 0 = one-wave / MFMA kernels, 1 = work-group kernels (autotuner)
+    int var[3][kNumCls][2] = {};
+
+    // recorded HIP graphs (crsolve_set_graphs)
+    struct GraphEntry {
+        std::vector<const void*> key;
+        hipGraphExec_t exec;
+    };
+    bool graphs_on = false;
+    mutable std::vector<GraphEntry> graphs;
+    mutable hipStream_t cap_stream = nullptr;
+
     // per-kernel timing (crsolve_timing_enable / crsolve_timing_read)
     mutable bool timing = false;
     mutable std::vector<hipEvent_t> evpool;
@@ -148,8 +163,18 @@ struct crsolve_plan {
     mutable std::vector<int> reckid;
     crsolve_plan* timing_parent = nullptr;
 
+    void drop_graphs() const
+    {
+        for (GraphEntry& g : graphs)
+            (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
+
     ~crsolve_plan()
     {
+        drop_graphs();
+        if (cap_stream)
+            (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : evpool)
             (void)hipEventDestroy(e);
     }
@@ -175,7 +200,8 @@ struct Timed {
     const crsolve_plan* p;
     hipStream_t st;
     hipEvent_t b = nullptr;
-    Timed(const crsolve_plan* pp, int kid, hipStream_t s) : p(tplan(pp)), st(s)
+    Timed(const crsolve_plan* pp, int kid, hipStream_t s, int cls = 0, int f64 = 0)
+        : p(tplan(pp)), st(s)
     {
         if (!p->timing)
             return;
@@ -185,7 +211,7 @@ struct Timed {
             b = nullptr;
             return;
         }
-        p->reckid.push_back(kid);
+        p->reckid.push_back(kid | (cls << 8) | (f64 << 12));
         (void)hipEventRecord(a, st);
     }
     ~Timed()
@@ -202,10 +228,10 @@ struct Disp {
     template <int MT>
     static void elim(const Launch& L, const Seg* segs, const void* inA, const void* inB,
                      const void* iny, void* W, unsigned long long* flags, int mat, int rhs,
-                     hipStream_t st)
+                     hipStream_t st, int variant)
     {
-        if constexpr (MT <= 32) {
-            hipLaunchKernelGGL((crs::k_elim_w<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
+        if (MT <= 32 && variant == 0) {
+            hipLaunchKernelGGL((crs::k_elim_w<T, MT <= 32 ? MT : 32>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else {
@@ -217,14 +243,15 @@ struct Disp {
     }
     template <int MT>
     static void reduce(const Launch& L, const Seg* segs, const void* inA, const void* iny, void* W,
-                       const unsigned long long* flags, int mat, int rhs, hipStream_t st)
+                       const unsigned long long* flags, int mat, int rhs, hipStream_t st,
+                       int variant)
     {
-        if constexpr (MT == 16 || MT == 32) {
-            hipLaunchKernelGGL((crs::k_reduce_m<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
+        if ((MT == 16 || MT == 32) && variant == 0) {
+            hipLaunchKernelGGL((crs::k_reduce_m<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
-        } else if constexpr (MT == 64) {
-            hipLaunchKernelGGL((crs::k_reduce_t<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
+        } else if (MT == 64 && variant == 0) {
+            hipLaunchKernelGGL((crs::k_reduce_t<T, 64>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else {
@@ -235,10 +262,10 @@ struct Disp {
     }
     template <int MT>
     static void back(const Launch& L, const Seg* segs, const void* W, void* X,
-                     const unsigned long long* flags, hipStream_t st)
+                     const unsigned long long* flags, hipStream_t st, int variant)
     {
-        if constexpr (MT == 16 || MT == 32) {
-            hipLaunchKernelGGL((crs::k_back_m<T, MT>), dim3((unsigned)L.total), dim3(64), 0, st,
+        if ((MT == 16 || MT == 32) && variant == 0) {
+            hipLaunchKernelGGL((crs::k_back_m<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
         } else {
             constexpr int PW = 32;
@@ -294,8 +321,9 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
     const void* inA = L.userAB ? A : c.ws;
     const void* inB = L.userAB ? B : c.ws;
     const void* iny = L.userY ? y : c.ws;
-    Timed tm(c.p, KID_ELIM, c.st);
-#define CALL(MT) Disp<T>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st)
+    Timed tm(c.p, KID_ELIM, c.st, L.cls, L.f64);
+    const int v = c.p->var[0][L.cls][L.f64];
+#define CALL(MT) Disp<T>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st, v)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
@@ -305,8 +333,9 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
 {
     const void* inA = L.userAB ? A : c.ws;
     const void* iny = L.userY ? y : c.ws;
-    Timed tm(c.p, KID_REDUCE, c.st);
-#define CALL(MT) Disp<T>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st)
+    Timed tm(c.p, KID_REDUCE, c.st, L.cls, L.f64);
+    const int v = c.p->var[1][L.cls][L.f64];
+#define CALL(MT) Disp<T>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st, v)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
@@ -315,8 +344,9 @@ template <class T>
 void run_back(const Ctx& c, const Launch& L, void* x)
 {
     void* X = L.userX ? x : c.ws;
-    Timed tm(c.p, KID_BACK, c.st);
-#define CALL(MT) Disp<T>::template back<MT>(L, c.dsegs, c.ws, X, c.flags, c.st)
+    Timed tm(c.p, KID_BACK, c.st, L.cls, L.f64);
+    const int v = c.p->var[2][L.cls][L.f64];
+#define CALL(MT) Disp<T>::template back<MT>(L, c.dsegs, c.ws, X, c.flags, c.st, v)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
@@ -921,18 +951,100 @@ int write_refine_info(const Ctx& c, crsolve_info* info, const std::vector<double
     return CRSOLVE_OK;
 }
 
+// Records `enqueue` once per key into a HIP graph on the plan's capture
+// stream (tables are uploaded first, outside the recording, so the graph
+// holds kernel nodes only) and launches the graph on `st`.
+template <class F>
+int with_graph(const crsolve_plan* p, const std::vector<const void*>& key, char* ws,
+               hipStream_t st, F enqueue)
+{
+    for (const crsolve_plan::GraphEntry& g : p->graphs)
+        if (g.key == key)
+            return hipGraphLaunch(g.exec, st) == hipSuccess ? CRSOLVE_OK : CRSOLVE_EHIP;
+    int rc = upload(p, ws, st);
+    if (rc)
+        return rc;
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return CRSOLVE_EHIP;
+    if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return CRSOLVE_EHIP;
+    const crsolve_plan* tp = tplan(p);
+    const bool timing = tp->timing;
+    tp->timing = false;
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        tp->timing = timing;
+        return CRSOLVE_EHIP;
+    }
+    enqueue(make_ctx(p, ws, p->cap_stream));
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->cap_stream, &g);
+    tp->timing = timing;
+    if (ec != hipSuccess || !g)
+        return CRSOLVE_EHIP;
+    hipGraphExec_t e = nullptr;
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return CRSOLVE_EHIP;
+    }
+    (void)hipGraphDestroy(g);
+    p->graphs.push_back({key, e});
+    return hipGraphLaunch(e, st) == hipSuccess ? CRSOLVE_OK : CRSOLVE_EHIP;
+}
+
+std::vector<const void*> gkey(intptr_t kind, std::initializer_list<const void*> ptrs)
+{
+    std::vector<const void*> k{(const void*)kind};
+    k.insert(k.end(), ptrs.begin(), ptrs.end());
+    return k;
+}
+
+void enqueue_native_fs(const Ctx& c, const void* A, const void* B, const void* y, void* x,
+                       crsolve_info* info)
+{
+    init_flags(c);
+    levels_down(c, A, B, y, 1, 1);
+    levels_up(c, x);
+    finalize(c, info, 0);
+}
+
+void enqueue_refine_factor(const Ctx& c, const void* A, const void* B)
+{
+    for (const CvtLaunch& cl : c.p->cvt_factor0)
+        run_cvt(c, cl, A, B, nullptr);
+    init_flags(c);
+    levels_down(c, A, B, nullptr, 1, 0);
+}
+
+// One solve pass of the mixed form: d = A^{-1} r with the mixed factors
+// (first pass: r = y), x = d or x += d, then the FP64 residual and its norms.
+void enqueue_refine_pass(const Ctx& c, const void* A, const void* B, const void* y, void* x,
+                         bool first)
+{
+    if (first)
+        for (const CvtLaunch& cl : c.p->cvt_solve0)
+            run_cvt(c, cl, nullptr, nullptr, y);
+    levels_down(c, nullptr, nullptr, nullptr, 0, 1);
+    levels_up(c, x);
+    update(c, x, first ? 1 : 0);
+    residual(c, A, B, x, y, true);
+}
+
 // FP32 factorization with FP64 tail; on breakdown, the FP64 plan takes over.
 int factor_refine(const crsolve_plan* p, const void* A, const void* B, char* ws,
                   crsolve_info* info, hipStream_t st)
 {
     Ctx c = make_ctx(p, ws, st);
-    int rc = upload(p, ws, st);
-    if (rc)
-        return rc;
-    for (const CvtLaunch& cl : p->cvt_factor0)
-        run_cvt(c, cl, A, B, nullptr);
-    init_flags(c);
-    levels_down(c, A, B, nullptr, 1, 0);
+    int rc;
+    if (p->graphs_on) {
+        rc = with_graph(p, gkey(1, {A, B, ws}), ws, st,
+                        [&](const Ctx& g) { enqueue_refine_factor(g, A, B); });
+        if (rc)
+            return rc;
+    } else {
+        if ((rc = upload(p, ws, st)))
+            return rc;
+        enqueue_refine_factor(c, A, B);
+    }
     std::vector<unsigned long long> fl(p->batch);
     if (hipMemcpyAsync(fl.data(), c.flags, sizeof(unsigned long long) * p->batch,
                        hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -981,15 +1093,19 @@ int solve_refine(const crsolve_plan* p, char* ws, const void* A, const void* B, 
             return rc;
         return last_err();
     }
-    // x_0 = A^{-1} y with the mixed factors
-    for (const CvtLaunch& cl : p->cvt_solve0)
-        run_cvt(c, cl, nullptr, nullptr, y);
-    levels_down(c, nullptr, nullptr, nullptr, 0, 1);
-    levels_up(c, x);
-    update(c, x, 1);
+    auto pass = [&](bool first) -> int {
+        if (!p->graphs_on) {
+            enqueue_refine_pass(c, A, B, y, x, first);
+            return CRSOLVE_OK;
+        }
+        return with_graph(p, gkey(first ? 2 : 3, {A, B, y, x, ws}), ws, st,
+                          [&](const Ctx& g) { enqueue_refine_pass(g, A, B, y, x, first); });
+    };
+    // x_0 = A^{-1} y with the mixed factors, then its residual
+    if ((rc = pass(true)))
+        return rc;
     int it = 0;
     for (;;) {
-        residual(c, A, B, x, y, true);
         if ((rc = read_norms(c, nh)))
             return rc;
         bool done = true;
@@ -1003,10 +1119,9 @@ int solve_refine(const crsolve_plan* p, char* ws, const void* A, const void* B, 
         if (done || it >= p->max_refine)
             break;
         // d = A^{-1} r with the mixed factors (r was written where level 0
-        // reads its right-hand side), x += d
-        levels_down(c, nullptr, nullptr, nullptr, 0, 1);
-        levels_up(c, x);
-        update(c, x, 0);
+        // reads its right-hand side), x += d, new residual
+        if ((rc = pass(false)))
+            return rc;
         ++it;
     }
     if ((rc = write_refine_info(c, info, tab)))
@@ -1146,8 +1261,8 @@ int crsolve_timing_read(crsolve_plan* p, crsolve_kernel_time* out, int cap, int*
         float t = 0.f;
         if (hipEventElapsedTime(&t, p->evpool[2 * i], p->evpool[2 * i + 1]) != hipSuccess)
             return CRSOLVE_EHIP;
-        cnt[p->reckid[i]] += 1;
-        ms[p->reckid[i]] += t;
+        cnt[p->reckid[i] & 255] += 1;
+        ms[p->reckid[i] & 255] += t;
     }
     int j = 0;
     for (int kid = 0; kid < KID_COUNT; ++kid) {
@@ -1186,6 +1301,101 @@ int crsolve_residual(const crsolve_plan* p, void* ws, size_t ws_bytes, const voi
         return rc;
     for (int s = 0; s < p->batch; ++s)
         rel[s] = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
+    return last_err();
+}
+
+int crsolve_set_graphs(crsolve_plan* p, int enable)
+{
+    if (!p)
+        return CRSOLVE_EINVAL;
+    p->graphs_on = enable != 0;
+    if (!enable)
+        p->drop_graphs();
+    if (p->fb)
+        p->fb->graphs_on = false;
+    return CRSOLVE_OK;
+}
+
+int crsolve_set_tuning(crsolve_plan* p, const char* choice)
+{
+    if (!p || !choice)
+        return CRSOLVE_EINVAL;
+    // tokens "r<role>c<class>f<precision>=<variant>;"
+    const char* q = choice;
+    while (*q) {
+        int r, c, f, v, n = 0;
+        if (std::sscanf(q, "r%dc%df%d=%d;%n", &r, &c, &f, &v, &n) != 4 || n == 0)
+            return CRSOLVE_EINVAL;
+        if (r < 0 || r > 2 || c < 0 || c >= kNumCls || f < 0 || f > 1 || v < 0 || v > 1)
+            return CRSOLVE_EINVAL;
+        p->var[r][c][f] = v;
+        q += n;
+    }
+    p->drop_graphs();
+    return CRSOLVE_OK;
+}
+
+int crsolve_autotune(crsolve_plan* p, const void* A, const void* B, const void* y, void* ws,
+                     size_t ws_bytes, void* x, void* stream, char* choice, size_t cap)
+{
+    if (!p || !choice || cap < 2)
+        return CRSOLVE_EINVAL;
+    if (p->sched != CRSOLVE_SCHED_CR || p->prec != CRSOLVE_PREC_NATIVE)
+        return CRSOLVE_EUNSUPPORTED;
+    int rc = check_ws(p, ws, ws_bytes);
+    if (rc)
+        return rc;
+    const size_t es = io_esz(p);
+    if (!aligned(A, es) || (any_B(p) && !aligned(B, es)) || !aligned(y, es) || !aligned(x, es))
+        return CRSOLVE_EINVAL;
+    const bool graphs = p->graphs_on;
+    p->graphs_on = false;
+    hipStream_t st = (hipStream_t)stream;
+    double t[2][3][kNumCls][2] = {};
+    bool seen[3][kNumCls][2] = {};
+    for (int v = 0; v < 2; ++v) {
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < kNumCls; ++c)
+                for (int f = 0; f < 2; ++f)
+                    p->var[r][c][f] = v;
+        Ctx c = make_ctx(p, ws, st);
+        for (int rep = 0; rep < 3; ++rep) {
+            if (rep == 1)
+                crsolve_timing_enable(p, 1);
+            if ((rc = upload(p, c.ws, st)))
+                return rc;
+            enqueue_native_fs(c, A, B, y, x, nullptr);
+        }
+        if (hipStreamSynchronize(st) != hipSuccess)
+            return CRSOLVE_EHIP;
+        for (size_t i = 0; i < p->reckid.size(); ++i) {
+            const int kid = p->reckid[i] & 255, cls = (p->reckid[i] >> 8) & 15,
+                      f64 = (p->reckid[i] >> 12) & 1;
+            if (kid > KID_BACK)
+                continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p->evpool[2 * i], p->evpool[2 * i + 1]) != hipSuccess)
+                return CRSOLVE_EHIP;
+            t[v][kid][cls][f64] += ms;
+            seen[kid][cls][f64] = true;
+        }
+        crsolve_timing_enable(p, 0);
+    }
+    std::string out;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < kNumCls; ++c)
+            for (int f = 0; f < 2; ++f) {
+                const int v = (seen[r][c][f] && t[1][r][c][f] < t[0][r][c][f]) ? 1 : 0;
+                p->var[r][c][f] = v;
+                if (seen[r][c][f])
+                    out += "r" + std::to_string(r) + "c" + std::to_string(c) + "f" +
+                           std::to_string(f) + "=" + std::to_string(v) + ";";
+            }
+    p->drop_graphs();
+    p->graphs_on = graphs;
+    if (out.size() + 1 > cap)
+        return CRSOLVE_EINVAL;
+    std::memcpy(choice, out.c_str(), out.size() + 1);
     return last_err();
 }
 
@@ -1272,13 +1482,15 @@ int crsolve_factor_solve(crsolve_plan* p, const void* A, const void* B, const vo
             return rc;
         return solve_refine(p, (char*)ws, A, B, y, x, info, (hipStream_t)stream);
     }
+    if (p->graphs_on) {
+        rc = with_graph(p, gkey(0, {A, B, y, x, ws, info}), (char*)ws, (hipStream_t)stream,
+                        [&](const Ctx& g) { enqueue_native_fs(g, A, B, y, x, info); });
+        return rc ? rc : last_err();
+    }
     Ctx c = make_ctx(p, ws, stream);
     if ((rc = upload(p, c.ws, c.st)))
         return rc;
-    init_flags(c);
-    levels_down(c, A, B, y, 1, 1);
-    levels_up(c, x);
-    finalize(c, info, 0);
+    enqueue_native_fs(c, A, B, y, x, info);
     return last_err();
 }
 

@@ -123,6 +123,39 @@ class Solver:
         return self.plan.residual(_ptr(self.ws), _ptr(A), _ptr(B), _ptr(x), _ptr(y),
                                   _stream(self.device))
 
+    def set_graphs(self, enable=True):
+        """Record each distinct call once into a HIP graph and replay it."""
+        self.plan.set_graphs(enable)
+
+    def autotune(self, A, B, y, cache=None):
+        """Pick the faster kernel variant per (role, block-size class,
+        precision) on this data (overwrites the workspace and a scratch x).
+        With ``cache`` (a JSON file path, default $CRSOLVE_TUNE_CACHE) a
+        previous choice for the same classes is reused and new ones are
+        stored."""
+        import json
+        import os
+        cache = cache or os.environ.get("CRSOLVE_TUNE_CACHE")
+        key = "|".join(sorted({"m%d_k%d" % (m, k) for m, k in zip(self.ms, self.ks)})) + \
+            "|%s|%s" % (self.dtype, self.plan.precision)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+            if key in table:
+                self.plan.set_tuning(table[key])
+                return table[key]
+        self._mat(A, B)
+        self._rhs(y)
+        x = torch.empty_like(y)
+        choice = self.plan.autotune(_ptr(A), _ptr(B), _ptr(y), _ptr(self.ws), _ptr(x),
+                                    _stream(self.device))
+        if cache:
+            table[key] = choice
+            with open(cache, "w") as fh:
+                json.dump(table, fh, indent=1)
+        return choice
+
     def timing(self, enable=True):
         """Per-kernel HIP-event timing of this solver's launches."""
         self.plan.timing(enable)
