@@ -140,7 +140,7 @@ def cpu_baseline(s, budget_s: float):
                       "reduction, %d solve(s) in %.1f s" % (s.N, s.m, s.k, reps, el)}
 
 
-def time_form(torch, sol, A, B, y, x, steps, warmup):
+def timed_steps(torch, sol, A, B, y, x, steps, warmup):
     for _ in range(warmup):
         sol.factor_solve(A, B, y, x)
     torch.cuda.synchronize()
@@ -150,15 +150,24 @@ def time_form(torch, sol, A, B, y, x, steps, warmup):
         sol.factor_solve(A, B, y, x)
     ev1.record()
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / steps
-    # per-kernel durations from HIP events bracketing each launch, same steps again
+    return ev0.elapsed_time(ev1) / steps
+
+
+def time_form(torch, sol, A, B, y, x, steps, warmup):
+    """Step time with the launch sequence replayed as a HIP graph, the eager
+    step time, and per-kernel event timings of eager steps."""
+    sol.set_graphs(True)
+    ms = timed_steps(torch, sol, A, B, y, x, steps, warmup)
+    sol.set_graphs(False)
+    ms_eager = timed_steps(torch, sol, A, B, y, x, steps, 1)
+    # per-kernel durations from HIP events bracketing each launch
     sol.timing(True)
     for _ in range(steps):
         sol.factor_solve(A, B, y, x)
     kt = sol.timing_read()
     sol.timing(False)
     torch.cuda.synchronize()
-    return ms, {kn: (cnt / steps, tot / steps) for kn, (cnt, tot) in kt.items()}
+    return ms, ms_eager, {kn: (cnt / steps, tot / steps) for kn, (cnt, tot) in kt.items()}
 
 
 def kernel_source_hash():
@@ -258,7 +267,8 @@ def main():
         else:
             sol = Solver([s.N], [s.m], [s.k], dtype=torch.complex128, precision="fp32_refine",
                          device=dev, rtol=RTOL, max_refine=30, fp64_tail_blocks=TAIL)
-        ms, per_step = time_form(torch, sol, A, B, y, x, args.steps, args.warmup)
+        tuning = sol.autotune(A, B, y) if form == "fp64" else None
+        ms, ms_eager, per_step = time_form(torch, sol, A, B, y, x, args.steps, args.warmup)
         info = sol.info_host()[0]
         if info["status"] != 0:
             raise SystemExit("%s: factorization failed: %s" % (form, info))
@@ -267,6 +277,8 @@ def main():
         mod = step_model(form, s.N, s.m, s.k, iters)
         forms[form] = {
             "ms_per_step": ms,
+            "ms_per_step_eager": ms_eager,
+            "tuning": tuning,
             "value": s.N / (ms * 1e-3),
             "rel_residual": rel,
             "certified": bool(rel <= RTOL),

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int n
                 }
                 __syncthreads();
                 if (tid == 0) {
-                    sL[c * LD + c] = cx<T>{sq, T(0)};
+                    sL[c * LD + c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
                     sInv[c] = inv;
                     if (!(dg > T(0)))
                         sFail = 1;
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int n
             }
             __syncthreads();
             for (int c = tid; c < m; c += NT)
-                sInv[c] = T(1) / sL[c * LD + c].r;
+                sInv[c] = sL[c * LD + c].i;
         }
         // forward substitution on the operands of Eq. (Formulas)
         for (int src = 0; src < 3; ++src) {
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(NT) void k_back(const Seg* __restrict__ segs, int n
         }
         __syncthreads();
         for (int c = tid; c < m; c += NT)
-            sInv[c] = T(1) / sL[c * LD + c].r;
+            sInv[c] = sL[c * LD + c].i;
         for (int c0 = 0; c0 < k; c0 += PW) {
             const int cw = min(PW, k - c0);
             __syncthreads();

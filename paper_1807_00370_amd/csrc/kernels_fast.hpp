@@ -61,6 +61,19 @@ __device__ __forceinline__ cx<T> czero()
     return cx<T>{T(0), T(0)};
 }
 
+// 1 / sqrt(d) from the hardware reciprocal square root and one Newton step
+// (relative error about the unit roundoff); NaN for d < 0, inf for d = 0.
+__device__ __forceinline__ double rsqrt_nr(double d)
+{
+    const double r = __builtin_amdgcn_rsq(d);
+    return r * fma(-0.5 * d * r, r, 1.5);
+}
+__device__ __forceinline__ float rsqrt_nr(float d)
+{
+    const float r = __builtin_amdgcn_rsqf(d);
+    return r * fmaf(-0.5f * d * r, r, 1.5f);
+}
+
 // MFMA 16x16x4 lane layout (wave64, checked on gfx950): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register v of lane l
 // holds D[row][l % 16] with row = 4 (l / 16) + v for the f32 instruction and
@@ -222,11 +235,11 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
                     // s = -(sum_u L[r][u] conj(L[c][u])); the pivot is lane c's
                     const cx<T> v{a[c].r + s0.r + s1.r, a[c].i + s0.i + s1.i};
                     const T dg = __shfl(v.r, c);
-                    const T sq = sqrt(dg);
-                    const T inv = T(1) / sq;
+                    const T inv = rsqrt_nr(dg);
+                    const T sq = dg * inv;
                     fail |= !(dg > T(0));
                     if (lane == c)
-                        a[c] = cx<T>{sq, T(0)};
+                        a[c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
                     else
                         a[c] = cx<T>{v.r * inv, v.i * inv};
                     if (lane >= c && lane < m)
@@ -235,6 +248,8 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
                         sInv[c] = inv;
                     __syncthreads();
                 }
+                // keep the next step's loads from being hoisted (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
             }
             if (lane == 0)
                 sFail = fail;
@@ -247,7 +262,7 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
                 sL[e] = Lg[e];
             __syncthreads();
             for (int c = lane; c < m; c += 64)
-                sInv[c] = T(1) / sL[c * (c + 1) / 2 + c].r;
+                sInv[c] = sL[c * (c + 1) / 2 + c].i;
         }
         __syncthreads();
 
@@ -301,20 +316,17 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
                         x[r] = yp[r * k + col];
             }
             // forward substitution, L by broadcast from LDS; each row's sum
-            // runs on two independent chains
+            // runs on four independent chains
 #pragma unroll
             for (int r = 0; r < MT; ++r) {
                 if (r < m) {
-                    cx<T> v0 = x[r], v1 = czero<T>();
+                    cx<T> v[4] = {x[r], czero<T>(), czero<T>(), czero<T>()};
 #pragma unroll
-                    for (int u = 0; u + 1 < r; u += 2) {
-                        msub(v0, sL[r * (r + 1) / 2 + u], x[u]);
-                        msub(v1, sL[r * (r + 1) / 2 + u + 1], x[u + 1]);
-                    }
-                    if (r & 1)
-                        msub(v0, sL[r * (r + 1) / 2 + r - 1], x[r - 1]);
+                    for (int u = 0; u < r; ++u)
+                        msub(v[u & 3], sL[r * (r + 1) / 2 + u], x[u]);
                     const T iv = sInv[r];
-                    x[r] = cx<T>{(v0.r + v1.r) * iv, (v0.i + v1.i) * iv};
+                    x[r] = cx<T>{((v[0].r + v[1].r) + (v[2].r + v[3].r)) * iv,
+                                 ((v[0].i + v[1].i) + (v[2].i + v[3].i)) * iv};
                 }
             }
             if (act) {
@@ -688,7 +700,7 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_back_m(const Seg* 
             sL[e] = L[e];
         __syncthreads();
         for (int c = lane; c < m; c += 64)
-            sInv[c] = T(1) / sL[c * (c + 1) / 2 + c].r;
+            sInv[c] = sL[c * (c + 1) / 2 + c].i;
         for (int c0 = 0; c0 < k; c0 += WC) {
             const int cw = min(WC, k - c0);
             __syncthreads();
