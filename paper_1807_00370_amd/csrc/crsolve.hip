@@ -29,6 +29,7 @@
 #include "kernels.hpp"
 #include "kernels_fast.hpp"
 #include "kernels_refine.hpp"
+#include "kernels_big.hpp"
 
 using crs::CvtJob;
 using crs::cx;
@@ -37,8 +38,9 @@ using crs::Seg;
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kNumCls = 5;
-constexpr int kClsM[kNumCls] = {4, 8, 16, 32, 64};
+constexpr int kNumCls = 6;
+constexpr int kClsM[kNumCls] = {4, 8, 16, 32, 64, 256};
+constexpr int kBig = 5; // tiled kernels (kernels_big.hpp) for 64 < m <= 256
 constexpr size_t kAlign = 256;
 constexpr int kMaxGrid = 1 << 16; // work-group kernels loop grid-stride above this grid
 
@@ -76,6 +78,7 @@ struct LevelSpec {
     int n = 0, ne = 0, nk = 0;
     int f64 = 1;
     int64_t oL = 0, oP = 0, oQ = 0, og = 0, oAo = 0, oBo = 0, oyo = 0; // ws, level type
+    int64_t oD = 0;                                                   // big blocks only
     int64_t oA = 0, oB = 0, oy = 0;                                   // inputs, level type
     bool userAB = false, userY = false, userX = false;
     int64_t ox = 0, xo = 0, xs = 1;
@@ -102,12 +105,14 @@ enum KernelId {
     KID_RESIDUAL,
     KID_NORMS,
     KID_UPDATE,
+    KID_POTRF,
+    KID_TRSM,
     KID_COUNT
 };
 const char* const kKernelName[KID_COUNT] = {"k_elim",       "k_reduce",   "k_back",
                                             "k_grad",       "k_flags_init", "k_finalize",
                                             "k_convert",    "k_residual", "k_norms",
-                                            "k_update"};
+                                            "k_update",     "k_potrf_big", "k_trsm_big"};
 
 } // namespace
 
@@ -314,6 +319,28 @@ Ctx make_ctx(const crsolve_plan* p, void* ws, void* stream)
     return c;
 }
 
+// Largest per-block extents over the segments of a launch of the tiled
+// kernels: 16-row tiles S, 16-column strips of the right-hand side K16, and
+// the 32-wide counts T32, K32 of the reduced-system tiles.
+struct BigDims {
+    int S = 0, K16 = 0, T32 = 0, K32 = 0;
+};
+BigDims big_dims(const crsolve_plan* p, const Launch& L)
+{
+    BigDims b;
+    for (int i = L.seg0; i < L.seg0 + L.nseg; ++i) {
+        const Seg& g = p->segs[i];
+        b.S = std::max(b.S, (g.m + 15) / 16);
+        b.K16 = std::max(b.K16, (g.k + 15) / 16);
+        b.T32 = std::max(b.T32, (g.m + 31) / 32);
+        b.K32 = std::max(b.K32, (g.k + 31) / 32);
+    }
+    return b;
+}
+
+// Grid of the tiled kernels: a multiple of 8 work-groups (see xcd_item).
+unsigned grid8(int64_t items) { return (unsigned)((items + 7) / 8 * 8); }
+
 template <class T>
 void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const void* y, int mat,
               int rhs)
@@ -321,6 +348,23 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
     const void* inA = L.userAB ? A : c.ws;
     const void* inB = L.userAB ? B : c.ws;
     const void* iny = L.userY ? y : c.ws;
+    if (L.cls == kBig) {
+        const BigDims b = big_dims(c.p, L);
+        if (mat) {
+            Timed tm(c.p, KID_POTRF, c.st, L.cls, L.f64);
+            hipLaunchKernelGGL((crs::k_potrf_big<T>), dim3((unsigned)L.total), dim3(256), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, (const cx<T>*)inA, (cx<T>*)c.ws,
+                               c.flags);
+        }
+        const int ns = (mat ? 2 * b.S : 0) + (rhs ? b.K16 : 0);
+        if (ns > 0) {
+            Timed tm(c.p, KID_TRSM, c.st, L.cls, L.f64);
+            hipLaunchKernelGGL((crs::k_trsm_big<T>), dim3(grid8(L.total * ns)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, ns, mat, rhs, (const cx<T>*)inB,
+                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+        }
+        return;
+    }
     Timed tm(c.p, KID_ELIM, c.st, L.cls, L.f64);
     const int v = c.p->var[0][L.cls][L.f64];
 #define CALL(MT) Disp<T>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st, v)
@@ -334,6 +378,15 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
     const void* inA = L.userAB ? A : c.ws;
     const void* iny = L.userY ? y : c.ws;
     Timed tm(c.p, KID_REDUCE, c.st, L.cls, L.f64);
+    if (L.cls == kBig) {
+        const BigDims b = big_dims(c.p, L);
+        const int nt = (mat ? b.T32 * (b.T32 + 1) / 2 + b.T32 * b.T32 : 0) + (rhs ? b.T32 * b.K32 : 0);
+        if (nt > 0)
+            hipLaunchKernelGGL((crs::k_reduce_big<T>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, mat, rhs, (const cx<T>*)inA,
+                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+        return;
+    }
     const int v = c.p->var[1][L.cls][L.f64];
 #define CALL(MT) Disp<T>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st, v)
     CRS_BY_CLASS(L.cls, CALL)
@@ -345,6 +398,13 @@ void run_back(const Ctx& c, const Launch& L, void* x)
 {
     void* X = L.userX ? x : c.ws;
     Timed tm(c.p, KID_BACK, c.st, L.cls, L.f64);
+    if (L.cls == kBig) {
+        const BigDims b = big_dims(c.p, L);
+        hipLaunchKernelGGL((crs::k_back_big<T>), dim3(grid8(L.total * b.K16)), dim3(64), 0, c.st,
+                           c.dsegs + L.seg0, L.nseg, L.total, b.K16, (const cx<T>*)c.ws, (cx<T>*)X,
+                           c.flags);
+        return;
+    }
     const int v = c.p->var[2][L.cls][L.f64];
 #define CALL(MT) Disp<T>::template back<MT>(L, c.dsegs, c.ws, X, c.flags, c.st, v)
     CRS_BY_CLASS(L.cls, CALL)
@@ -355,6 +415,13 @@ template <class T>
 void run_grad(const Ctx& c, const Launch& L, const void* x, const void* lam, void* gA, void* gB)
 {
     Timed tm(c.p, KID_GRAD, c.st);
+    if (L.cls == kBig) {
+        const BigDims b = big_dims(c.p, L);
+        hipLaunchKernelGGL((crs::k_grad_big<T>), dim3(grid8(L.total * b.T32 * b.T32)), dim3(64), 0,
+                           c.st, c.dsegs + L.seg0, L.nseg, L.total, b.T32 * b.T32, (const cx<T>*)x,
+                           (const cx<T>*)lam, (cx<T>*)gA, (cx<T>*)gB);
+        return;
+    }
 #define CALL(MT) Disp<T>::template grad<MT>(L, c.dsegs, x, lam, gA, gB, c.st)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
@@ -447,6 +514,7 @@ void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count cou
                     g.oAo = v.oAo; g.oBo = v.oBo; g.oyo = v.oyo;
                     g.oA = v.oA; g.oB = v.oB; g.oy = v.oy;
                     g.ox = v.ox; g.xo = v.xo; g.xs = v.xs;
+                    g.oD = v.oD;
                     if (p->sched == CRSOLVE_SCHED_CR) {
                         g.d = 1;
                         g.e0 = 0; g.es = 2; g.ne = v.ne;
@@ -532,6 +600,7 @@ int build_plan(crsolve_plan* p)
     int maxlev = 0;
     for (int s = 0; s < p->batch; ++s) {
         const int64_t mm = (int64_t)p->m[s] * p->m[s], mk = (int64_t)p->m[s] * p->k[s];
+        const int64_t dtiles = (int64_t)((p->m[s] + 15) / 16) * 256; // inverse diagonal tiles
         std::vector<LevelSpec>& L = p->lv[s];
         if (p->sched == CRSOLVE_SCHED_CR) {
             for (int v = p->N[s]; v > 0; v /= 2) {
@@ -559,6 +628,8 @@ int build_plan(crsolve_plan* p)
                 v.oQ = a.take(v.ne * mm, es);
                 v.oAo = a.take(v.nk * mm, es);
                 v.oBo = a.take(std::max(v.nk - 1, 0) * mm, es);
+                if (p->cls[s] == kBig)
+                    v.oD = a.take(v.ne * dtiles, es);
             }
             for (size_t l = 0; l < L.size(); ++l) {
                 LevelSpec& v = L[l];
@@ -627,6 +698,7 @@ int build_plan(crsolve_plan* p)
             const size_t es = e64;
             int64_t oL = a.take(N * mm, es), oP = a.take(N * mm, es), oQ = a.take(N * mm, es),
                     og = a.take(N * mk, es);
+            const int64_t oD = p->cls[s] == kBig ? a.take(N * dtiles, es) : 0;
             int64_t bA[2], bB[2], by[2];
             for (int b = 0; b < 2; ++b) {
                 bA[b] = a.take(N * mm, es);
@@ -639,7 +711,7 @@ int build_plan(crsolve_plan* p)
                 v.ne = N;
                 v.nk = l < D ? N : 0;
                 v.f64 = 1;
-                v.oL = oL; v.oP = oP; v.oQ = oQ; v.og = og;
+                v.oL = oL; v.oP = oP; v.oQ = oQ; v.og = og; v.oD = oD;
                 v.oAo = bA[(l + 1) & 1]; v.oBo = bB[(l + 1) & 1]; v.oyo = by[(l + 1) & 1];
                 if (l == 0) {
                     v.userAB = v.userY = true;
@@ -906,7 +978,14 @@ void residual(const Ctx& c, const void* A, const void* B, const void* x, const v
                        c.dsegs + L.seg0, L.nseg, L.total, (const cx<double>*)A,                    \
                        (const cx<double>*)B, (const cx<double>*)x, (const cx<double>*)y, R,        \
                        L.f64 ? 0 : 1, part)
-        CRS_BY_CLASS(L.cls, CALL)
+        switch (L.cls) {
+        case 0: CALL(4); break;
+        case 1: CALL(8); break;
+        case 2: CALL(16); break;
+        case 3: CALL(32); break;
+        case 4: CALL(64); break;
+        default: CALL(256); break;
+        }
 #undef CALL
     }
     Timed tm(p, KID_NORMS, c.st);
@@ -1150,8 +1229,10 @@ int validate(const crsolve_desc* d)
     for (int s = 0; s < d->batch; ++s) {
         if (d->N[s] < 1 || d->m[s] < 1 || d->k[s] < 1)
             return CRSOLVE_EINVAL;
-        if (d->m[s] > 64)
+        if (d->m[s] > kClsM[kNumCls - 1])
             return CRSOLVE_EUNSUPPORTED;
+        if (d->m[s] > 64 && d->N[s] > (1 << 24))
+            return CRSOLVE_EUNSUPPORTED; // keeps the tiled kernels' work-item counts in range
         if ((int64_t)d->N[s] >= (1ll << 30))
             return CRSOLVE_EUNSUPPORTED;
     }

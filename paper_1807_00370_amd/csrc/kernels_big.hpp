@@ -1,0 +1,651 @@
+// Kernels of a reduction level for block sizes 64 < m <= 256 (the block 2D
+// Poisson workload has m = 256).  A block no longer fits in LDS, so every
+// step is cut into 16 x 16 MFMA tiles (real-pair 4-multiply complex form)
+// whose operands stream from L2:
+//
+//   k_potrf_big   one work-group per eliminated block: blocked left-looking
+//                 Cholesky L_p = chol(A_p) by 16-column panels.  The panel
+//                 update L[R][<I] L[I][<I]^H runs on MFMA, each 16 x 16
+//                 diagonal tile is factored in registers (one row per lane)
+//                 and its inverse D_I = L_II^{-1} is kept for the
+//                 substitutions; the tiles below become S_R D_I^H.
+//   k_trsm_big    one wave per (eliminated block, 16-column strip of
+//                 [B_p^H | B_{p-d} | y_p]): blocked forward substitution
+//                 X_I = D_I (G_I - L[I][<I] X_{<I}), the Section 4 recipe
+//                 L \ G for the three operands of Eq. (Formulas).
+//   k_reduce_big  one wave per (kept block, 32 x 32 tile) of the reduced
+//                 system A' = A_q - P_l^H P_l - Q_r^H Q_r (lower triangle),
+//                 B' = -P_r^H Q_r, y' = y_q - P_l^H g_l - Q_r^H g_r.
+//   k_back_big    one wave per (eliminated block, 16-column strip of x_p):
+//                 blocked back substitution of
+//                 L^H x_p = g_p - Q_p x_{p-d} - P_p x_{p+d}.
+//   k_grad_big    one wave per (block row, 32 x 32 tile) of the adjoint's
+//                 gradient blocks.
+//
+// Storage for these sizes: L_p as a full m x m row-major slot (lower
+// triangle used; the diagonal holds {L_cc, 1 / L_cc} like every other
+// factor) and the inverse diagonal tiles D_I (16 x 16 row-major, lower
+// triangular) at Seg::oD.  A trailing partial tile is padded with the
+// identity, so the padding never reaches a stored value.
+#pragma once
+
+#include "kernels_fast.hpp"
+
+namespace crs {
+
+// Work item of this work-group when the 1-D grid (a multiple of 8 groups) is
+// dealt round-robin over the 8 XCDs: consecutive items then run on one XCD,
+// whose L2 holds the operands they share.
+__device__ __forceinline__ int64_t xcd_item()
+{
+    const int64_t b = blockIdx.x, q = gridDim.x >> 3;
+    return (b & 7) * q + (b >> 3);
+}
+
+// Operand of a wave-level product: element (o, t) at p[o * so + t * st] for
+// o < no (zero beyond), where o is the row of a left operand or the column
+// of a right operand and t the contraction index.
+template <class T>
+struct WOp {
+    const cx<T>* p;
+    int so, st, no;
+};
+
+// (cr, ci)[a][b] += opA(A) opB(B) over kd contraction steps for the RM x RN
+// tiles of 16 x 16: rows 16 a + i of the left operand, columns 16 b + j of the
+// right one; CA / CB conjugate the operand.  Operands are loaded G k-steps at
+// a time, one group ahead of the MFMAs that consume the previous group.
+template <class T, int RM, int RN, bool CA, bool CB, int G>
+__device__ __forceinline__ void wave_mm(typename MF<T>::v4 (&cr)[RM][RN],
+                                        typename MF<T>::v4 (&ci)[RM][RN], const WOp<T> A,
+                                        const WOp<T> B, int kd)
+{
+    const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+    const int ng = (kd + 4 * G - 1) / (4 * G);
+    if (ng <= 0)
+        return;
+    const cx<T>* pa[RM];
+    const cx<T>* pb[RN];
+    bool oa[RM], ob[RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+        const int o = 16 * i + cc;
+        oa[i] = o < A.no;
+        pa[i] = A.p + ((oa[i] ? o : 0) * A.so + kr * A.st);
+    }
+#pragma unroll
+    for (int j = 0; j < RN; ++j) {
+        const int o = 16 * j + cc;
+        ob[j] = o < B.no;
+        pb[j] = B.p + ((ob[j] ? o : 0) * B.so + kr * B.st);
+    }
+    const int sa = 4 * A.st, sb = 4 * B.st;
+    cx<T> xa0[RM][G], yb0[RN][G], xa1[RM][G], yb1[RN][G];
+    auto load = [&](cx<T>(&xa)[RM][G], cx<T>(&yb)[RN][G], int g) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int ks = g * G + u;
+            const bool ok = 4 * ks + kr < kd;
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+                xa[i][u] = (ok && oa[i]) ? pa[i][ks * sa] : czero<T>();
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+                yb[j][u] = (ok && ob[j]) ? pb[j][ks * sb] : czero<T>();
+        }
+    };
+    auto comp = [&](const cx<T>(&xa)[RM][G], const cx<T>(&yb)[RN][G]) {
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+                for (int j = 0; j < RN; ++j) {
+                    const T ar = xa[i][u].r, ai = CA ? -xa[i][u].i : xa[i][u].i;
+                    const T br = yb[j][u].r, bi = CB ? -yb[j][u].i : yb[j][u].i;
+                    cr[i][j] = MF<T>::mma(ar, br, cr[i][j]);
+                    cr[i][j] = MF<T>::mma(-ai, bi, cr[i][j]);
+                    ci[i][j] = MF<T>::mma(ar, bi, ci[i][j]);
+                    ci[i][j] = MF<T>::mma(ai, br, ci[i][j]);
+                }
+    };
+    load(xa0, yb0, 0);
+    for (int g = 0; g < ng; g += 2) {
+        if (g + 1 < ng)
+            load(xa1, yb1, g + 1);
+        comp(xa0, yb0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (g + 1 < ng) {
+            if (g + 2 < ng)
+                load(xa0, yb0, g + 2);
+            comp(xa1, yb1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <class T, int RM, int RN>
+__device__ __forceinline__ void zero_acc(typename MF<T>::v4 (&cr)[RM][RN],
+                                         typename MF<T>::v4 (&ci)[RM][RN])
+{
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) {
+            cr[i][j] = typename MF<T>::v4{0, 0, 0, 0};
+            ci[i][j] = typename MF<T>::v4{0, 0, 0, 0};
+        }
+}
+
+// Orders the LDS accesses of one wave: stores before the call are seen by
+// loads after it from any lane of the same wave (a wave's LDS operations
+// complete in order; the fences keep the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------- k_potrf_big
+
+template <class T>
+__global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs, int nseg,
+                                                   int64_t total, const cx<T>* __restrict__ inA,
+                                                   cx<T>* __restrict__ W,
+                                                   unsigned long long* __restrict__ flags)
+{
+    using v4 = typename MF<T>::v4;
+    __shared__ cx<T> sT[16 * 17]; // diagonal tile of L (row-major, leading dimension 17)
+    __shared__ int sFail;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, kr = lane >> 4, cc = lane & 15;
+    const int64_t w = blockIdx.x;
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int p = s.e0 + (int)t * s.es;
+    const int m = s.m, S = (m + 15) >> 4;
+    if ((flags[s.sys] >> 40) < (unsigned long long)s.level)
+        return; // broke down at an earlier level
+    const int64_t mm = (int64_t)m * m;
+    const cx<T>* Ap = inA + s.oA + (int64_t)p * mm;
+    cx<T>* Lg = W + s.oL + t * mm;
+    cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
+    if (tid == 0)
+        sFail = 0;
+    for (int I = 0; I < S; ++I) {
+        const int c0 = 16 * I;
+        // panel column I: S_R = A[R][I] - L[R][<I] L[I][<I]^H for R >= I (the
+        // Hermitian reading of A: lower triangle of the diagonal tile only)
+        for (int R = I + wv; R < S; R += 4) {
+            v4 cr[1][1], ci[1][1];
+            zero_acc<T, 1, 1>(cr, ci);
+            wave_mm<T, 1, 1, false, true, 4>(cr, ci, WOp<T>{Lg + (int64_t)16 * R * m, m, 1, m - 16 * R},
+                                             WOp<T>{Lg + (int64_t)c0 * m, m, 1, m - c0}, c0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * R + MF<T>::row(kr, v), j = c0 + cc;
+                if (i < m && j < m && (R > I || j <= i)) {
+                    const cx<T> a = Ap[(int64_t)i * m + j];
+                    Lg[(int64_t)i * m + j] = cx<T>{a.r - cr[0][0][v], a.i - ci[0][0][v]};
+                }
+            }
+        }
+        __syncthreads();
+        // diagonal tile (wave 0): lane r & 15 keeps row r in registers;
+        // left-looking Cholesky that publishes each finished column to LDS,
+        // where later columns read the rows of L by broadcast; then lane r
+        // forms column r of D = L_II^{-1} by forward substitution
+        if (wv == 0) {
+            const int r = lane & 15, gi = c0 + r;
+            const bool real = gi < m;
+            cx<T> a[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                if (real)
+                    a[u] = u <= r ? Lg[(int64_t)gi * m + c0 + u] : czero<T>();
+                else
+                    a[u] = u == r ? cx<T>{T(1), T(0)} : czero<T>();
+                if (u == r)
+                    a[u].i = T(0);
+            }
+            bool fail = false;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                cx<T> s0 = a[c], s1 = czero<T>();
+#pragma unroll
+                for (int u = 0; u + 1 < c; u += 2) {
+                    msub_cb(s0, a[u], sT[c * 17 + u]);
+                    msub_cb(s1, a[u + 1], sT[c * 17 + u + 1]);
+                }
+                if (c & 1)
+                    msub_cb(s0, a[c - 1], sT[c * 17 + c - 1]);
+                const cx<T> sv{s0.r + s1.r, s0.i + s1.i};
+                const T dg = __shfl(sv.r, c);
+                const T inv = rsqrt_nr(dg);
+                const T sq = dg * inv;
+                fail |= (c0 + c < m) && !(dg > T(0));
+                if (r == c)
+                    a[c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
+                else if (r > c)
+                    a[c] = cx<T>{sv.r * inv, sv.i * inv};
+                if (lane < 16)
+                    sT[r * 17 + c] = a[c];
+                wave_lds_sync();
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (lane < 16 && real) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (u <= r)
+                        Lg[(int64_t)gi * m + c0 + u] = a[u];
+            }
+            cx<T> z[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                cx<T> v = q == r ? cx<T>{T(1), T(0)} : czero<T>();
+#pragma unroll
+                for (int u = 0; u < q; ++u)
+                    msub(v, sT[q * 17 + u], z[u]);
+                const T iq = sT[q * 17 + q].i;
+                z[q] = cx<T>{v.r * iq, v.i * iq};
+            }
+            if (lane < 16) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    Dg[I * 256 + q * 16 + r] = z[q];
+            }
+            if (lane == 0 && fail)
+                sFail = 1;
+        }
+        __syncthreads();
+        // tiles below the diagonal: L[R][I] = S_R D_I^H, in place
+        for (int R = I + 1 + wv; R < S; R += 4) {
+            v4 cr[1][1], ci[1][1];
+            zero_acc<T, 1, 1>(cr, ci);
+            wave_mm<T, 1, 1, false, true, 4>(cr, ci,
+                                             WOp<T>{Lg + (int64_t)16 * R * m + c0, m, 1, m - 16 * R},
+                                             WOp<T>{Dg + I * 256, 16, 1, 16}, min(16, m - c0));
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * R + MF<T>::row(kr, v), j = c0 + cc;
+                if (i < m && j < m)
+                    Lg[(int64_t)i * m + j] = cx<T>{cr[0][0][v], ci[0][0][v]};
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && sFail)
+        atomicMin(&flags[s.sys], fail_key(s.level, s.ob0 + s.obs * p));
+}
+
+// -------------------------------------------------------------- k_trsm_big
+
+// Strips of a block: with_mat gives 2 S strips (columns of B_p^H, then of
+// B_{p-d}), with_rhs ceil(k / 16) strips of y_p after them.
+template <class T>
+__global__ __launch_bounds__(64) void k_trsm_big(const Seg* __restrict__ segs, int nseg,
+                                                 int64_t total, int nstrip, int with_mat,
+                                                 int with_rhs, const cx<T>* __restrict__ inB,
+                                                 const cx<T>* __restrict__ iny,
+                                                 cx<T>* __restrict__ W,
+                                                 const unsigned long long* __restrict__ flags)
+{
+    using v4 = typename MF<T>::v4;
+    const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
+    const int64_t li = xcd_item();
+    const int64_t w = li / nstrip;
+    int u = (int)(li - w * nstrip);
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int p = s.e0 + (int)t * s.es;
+    const int m = s.m, k = s.k, d = s.d, S = (m + 15) >> 4;
+    if ((flags[s.sys] >> 40) < (unsigned long long)s.level)
+        return;
+    const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
+    int src = 2;
+    if (with_mat) {
+        if (u < 2 * S)
+            src = u < S ? 0 : 1;
+        else
+            u -= 2 * S;
+    }
+    int c0;
+    if (src == 2) {
+        c0 = 16 * u;
+        if (!with_rhs || c0 >= k)
+            return;
+    } else {
+        c0 = 16 * (src == 0 ? u : u - S);
+        if (src == 0 ? p + d >= s.n : p - d < 0)
+            return;
+    }
+    const int nc = min(16, (src == 2 ? k : m) - c0);
+    // element (r, c) of the right-hand side is G[r * gr + c * gc]
+    const cx<T>* G;
+    int gr, gc;
+    cx<T>* out;
+    if (src == 0) {
+        G = inB + s.oB + (int64_t)p * mm; // B_p^H: conjugated below
+        gr = 1;
+        gc = m;
+        out = W + s.oP + t * mm;
+    } else if (src == 1) {
+        G = inB + s.oB + (int64_t)(p - d) * mm;
+        gr = m;
+        gc = 1;
+        out = W + s.oQ + t * mm;
+    } else {
+        G = iny + s.oy + (int64_t)p * mk;
+        gr = k;
+        gc = 1;
+        out = W + s.og + t * mk;
+    }
+    const int ldo = src == 2 ? k : m;
+    const cx<T>* Lg = W + s.oL + t * mm;
+    const cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
+    for (int I = 0; I < S; ++I) {
+        const int r0 = 16 * I;
+        v4 cr[1][1], ci[1][1];
+        zero_acc<T, 1, 1>(cr, ci);
+        wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{Lg + (int64_t)r0 * m, m, 1, m - r0},
+                                          WOp<T>{out + c0, 1, ldo, nc}, r0);
+        // w = G_I - acc stays in the accumulator layout: register v of lane
+        // (kr, cc) holds row MF::row(kr, v) of column cc, which is the right
+        // operand of contraction step v once the left operand D_I supplies
+        // column MF::row(kr, v) of its row cc
+        v4 xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = MF<T>::row(kr, v), r = r0 + rr;
+            cx<T> g = (r < m && cc < nc) ? G[r * gr + (c0 + cc) * gc] : czero<T>();
+            if (src == 0)
+                g.i = -g.i;
+            const T br = g.r - cr[0][0][v], bi = g.i - ci[0][0][v];
+            const cx<T> a = Dg[I * 256 + cc * 16 + rr];
+            xr = MF<T>::mma(a.r, br, xr);
+            xr = MF<T>::mma(-a.i, bi, xr);
+            xi = MF<T>::mma(a.r, bi, xi);
+            xi = MF<T>::mma(a.i, br, xi);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + MF<T>::row(kr, v);
+            if (r < m && cc < nc)
+                out[(int64_t)r * ldo + c0 + cc] = cx<T>{xr[v], xi[v]};
+        }
+        __syncthreads(); // the rows just stored are the next tiles' operands
+    }
+}
+
+// ------------------------------------------------------------ k_reduce_big
+
+// Tiles of a kept block (T32 = ceil(m / 32)): with_mat gives the
+// T32 (T32 + 1) / 2 lower tiles of A' and the T32^2 tiles of B', with_rhs the
+// T32 ceil(k / 32) tiles of y' after them.
+template <class T>
+__global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs, int nseg,
+                                                   int64_t total, int ntile, int with_mat,
+                                                   int with_rhs, const cx<T>* __restrict__ inA,
+                                                   const cx<T>* __restrict__ iny,
+                                                   cx<T>* __restrict__ W,
+                                                   const unsigned long long* __restrict__ flags)
+{
+    using v4 = typename MF<T>::v4;
+    const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
+    const int64_t li = xcd_item();
+    const int64_t w = li / ntile;
+    int u = (int)(li - w * ntile);
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int q = s.k0 + (int)t * s.ks;
+    const int m = s.m, k = s.k, d = s.d, n = s.n;
+    const int l = q - d, r = q + d;
+    const bool hasL = l >= 0, hasR = r < n;
+    const int64_t tl = hasL ? (l - s.e0) / s.es : 0, tr = hasR ? (r - s.e0) / s.es : 0;
+    const int64_t oi = s.out_by_pos ? q : t;
+    const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
+    if ((flags[s.sys] >> 40) <= (unsigned long long)s.level)
+        return; // the level's elimination broke down: stop this system
+    const int T32 = (m + 31) >> 5, nV = T32 * (T32 + 1) / 2, nF = T32 * T32;
+    int kind, ti, tj;
+    if (with_mat && u < nV + nF) {
+        if (u < nV) {
+            kind = 0;
+            ti = tri_row(u);
+            tj = u - ti * (ti + 1) / 2;
+        } else {
+            kind = 1;
+            u -= nV;
+            ti = u / T32;
+            tj = u % T32;
+            if (!hasR || r + d >= n)
+                return;
+        }
+    } else {
+        if (with_mat)
+            u -= nV + nF;
+        const int Tk = (k + 31) >> 5;
+        if (!with_rhs || u >= T32 * Tk)
+            return;
+        kind = 2;
+        ti = u / Tk;
+        tj = u % Tk;
+    }
+    const cx<T>* Pl = W + s.oP + tl * mm;
+    const cx<T>* Qr = W + s.oQ + tr * mm;
+    const cx<T>* Pr = W + s.oP + tr * mm;
+    const int i0 = 32 * ti, j0 = 32 * tj;
+    v4 cr[2][2], ci[2][2];
+    zero_acc<T, 2, 2>(cr, ci);
+    if (kind == 0) {
+        if (hasL)
+            wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Pl + i0, 1, m, m - i0},
+                                             WOp<T>{Pl + j0, 1, m, m - j0}, m);
+        if (hasR)
+            wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Qr + i0, 1, m, m - i0},
+                                             WOp<T>{Qr + j0, 1, m, m - j0}, m);
+        const cx<T>* Aq = inA + s.oA + q * mm;
+        cx<T>* Vo = W + s.oAo + oi * mm;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + 16 * a + MF<T>::row(kr, v), j = j0 + 16 * b + cc;
+                    if (i < m && j <= i) {
+                        const cx<T> x = Aq[i * m + j];
+                        cx<T> o{x.r - cr[a][b][v], x.i - ci[a][b][v]};
+                        if (i == j)
+                            o.i = T(0);
+                        Vo[i * m + j] = o;
+                    }
+                }
+    } else if (kind == 1) {
+        wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Pr + i0, 1, m, m - i0},
+                                         WOp<T>{Qr + j0, 1, m, m - j0}, m);
+        cx<T>* Fo = W + s.oBo + oi * mm;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + 16 * a + MF<T>::row(kr, v), j = j0 + 16 * b + cc;
+                    if (i < m && j < m)
+                        Fo[i * m + j] = cx<T>{-cr[a][b][v], -ci[a][b][v]};
+                }
+    } else {
+        const cx<T>* gl = W + s.og + tl * mk;
+        const cx<T>* gr = W + s.og + tr * mk;
+        if (hasL)
+            wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Pl + i0, 1, m, m - i0},
+                                             WOp<T>{gl + j0, 1, k, k - j0}, m);
+        if (hasR)
+            wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Qr + i0, 1, m, m - i0},
+                                             WOp<T>{gr + j0, 1, k, k - j0}, m);
+        const cx<T>* yq = iny + s.oy + q * mk;
+        cx<T>* vo = W + s.oyo + oi * mk;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + 16 * a + MF<T>::row(kr, v), c = j0 + 16 * b + cc;
+                    if (i < m && c < k) {
+                        const cx<T> x = yq[i * k + c];
+                        vo[i * k + c] = cx<T>{x.r - cr[a][b][v], x.i - ci[a][b][v]};
+                    }
+                }
+    }
+}
+
+// -------------------------------------------------------------- k_back_big
+
+template <class T>
+__global__ __launch_bounds__(64) void k_back_big(const Seg* __restrict__ segs, int nseg,
+                                                 int64_t total, int nstrip,
+                                                 const cx<T>* __restrict__ W,
+                                                 cx<T>* __restrict__ X,
+                                                 const unsigned long long* __restrict__ flags)
+{
+    using v4 = typename MF<T>::v4;
+    const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
+    const int64_t li = xcd_item();
+    const int64_t w = li / nstrip;
+    const int u = (int)(li - w * nstrip);
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int p = s.e0 + (int)t * s.es;
+    const int m = s.m, k = s.k, d = s.d, S = (m + 15) >> 4;
+    const int c0 = 16 * u;
+    if (c0 >= k)
+        return;
+    const int nc = min(16, k - c0);
+    const bool hasPrev = p - d >= 0, hasNext = p + d < s.n;
+    const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
+    cx<T>* xp = X + s.ox + (s.xo + s.xs * p) * mk;
+    if (flags[s.sys] != kNoFail) {
+        const T nan = T(NAN);
+        for (int e = lane; e < m * 16; e += 64)
+            if ((e & 15) < nc)
+                xp[(e >> 4) * k + c0 + (e & 15)] = cx<T>{nan, nan};
+        return;
+    }
+    const cx<T>* xm = X + s.ox + (s.xo + s.xs * (p - d)) * mk;
+    const cx<T>* xn = X + s.ox + (s.xo + s.xs * (p + d)) * mk;
+    const cx<T>* L = W + s.oL + t * mm;
+    const cx<T>* P = W + s.oP + t * mm;
+    const cx<T>* Q = W + s.oQ + t * mm;
+    const cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
+    const cx<T>* g = W + s.og + t * mk;
+    for (int I = S - 1; I >= 0; --I) {
+        const int r0 = 16 * I;
+        v4 cr[1][1], ci[1][1];
+        zero_acc<T, 1, 1>(cr, ci);
+        if (hasPrev)
+            wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{Q + (int64_t)r0 * m, m, 1, m - r0},
+                                              WOp<T>{xm + c0, 1, k, nc}, m);
+        if (hasNext)
+            wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{P + (int64_t)r0 * m, m, 1, m - r0},
+                                              WOp<T>{xn + c0, 1, k, nc}, m);
+        // sum over the tiles below of L[J][I]^H x_J
+        wave_mm<T, 1, 1, true, false, 4>(cr, ci, WOp<T>{L + (int64_t)(r0 + 16) * m + r0, 1, m, m - r0},
+                                         WOp<T>{xp + (int64_t)(r0 + 16) * k + c0, 1, k, nc},
+                                         m - r0 - 16);
+        // x_I = D_I^H (g_I - acc), with the accumulator as the right operand
+        // (see k_trsm_big); (D^H)[cc][rr] = conj(D[rr][cc])
+        v4 xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = MF<T>::row(kr, v), r = r0 + rr;
+            const cx<T> gg = (r < m && cc < nc) ? g[r * k + c0 + cc] : czero<T>();
+            const T br = gg.r - cr[0][0][v], bi = gg.i - ci[0][0][v];
+            const cx<T> a = Dg[I * 256 + rr * 16 + cc];
+            xr = MF<T>::mma(a.r, br, xr);
+            xr = MF<T>::mma(a.i, bi, xr);
+            xi = MF<T>::mma(a.r, bi, xi);
+            xi = MF<T>::mma(-a.i, br, xi);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + MF<T>::row(kr, v);
+            if (r < m && cc < nc)
+                xp[(int64_t)r * k + c0 + cc] = cx<T>{xr[v], xi[v]};
+        }
+        __syncthreads(); // the rows just stored are the next tiles' operands
+    }
+}
+
+// -------------------------------------------------------------- k_grad_big
+
+// gA_j = -lam_j x_j^H and gB_j = -(lam_{j+1} x_j^H + x_{j+1} lam_j^H), one
+// wave per (block row j, 32 x 32 tile); whole-system segments as in k_grad.
+template <class T>
+__global__ __launch_bounds__(64) void k_grad_big(const Seg* __restrict__ segs, int nseg,
+                                                 int64_t total, int ntile,
+                                                 const cx<T>* __restrict__ X,
+                                                 const cx<T>* __restrict__ Lam,
+                                                 cx<T>* __restrict__ gA, cx<T>* __restrict__ gB)
+{
+    using v4 = typename MF<T>::v4;
+    const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
+    const int64_t li = xcd_item();
+    const int64_t w = li / ntile;
+    const int u = (int)(li - w * ntile);
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int j = (int)(w - s.w0);
+    const int m = s.m, k = s.k, n = s.n, T32 = (m + 31) >> 5;
+    if (u >= T32 * T32)
+        return;
+    const int i0 = 32 * (u / T32), j0 = 32 * (u % T32);
+    const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
+    const cx<T>* l0 = Lam + s.oy + j * mk;
+    const cx<T>* x0 = X + s.ox + j * mk;
+    v4 cr[2][2], ci[2][2];
+    zero_acc<T, 2, 2>(cr, ci);
+    wave_mm<T, 2, 2, false, true, 2>(cr, ci, WOp<T>{l0 + (int64_t)i0 * k, k, 1, m - i0},
+                                     WOp<T>{x0 + (int64_t)j0 * k, k, 1, m - j0}, k);
+    cx<T>* ga = gA + s.oA + j * mm;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + 16 * a + MF<T>::row(kr, v), c = j0 + 16 * b + cc;
+                if (i < m && c < m)
+                    ga[i * m + c] = cx<T>{-cr[a][b][v], -ci[a][b][v]};
+            }
+    if (j + 1 >= n)
+        return;
+    zero_acc<T, 2, 2>(cr, ci);
+    wave_mm<T, 2, 2, false, true, 2>(cr, ci, WOp<T>{l0 + mk + (int64_t)i0 * k, k, 1, m - i0},
+                                     WOp<T>{x0 + (int64_t)j0 * k, k, 1, m - j0}, k);
+    wave_mm<T, 2, 2, false, true, 2>(cr, ci, WOp<T>{x0 + mk + (int64_t)i0 * k, k, 1, m - i0},
+                                     WOp<T>{l0 + (int64_t)j0 * k, k, 1, m - j0}, k);
+    cx<T>* gb = gB + s.oB + j * mm;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + 16 * a + MF<T>::row(kr, v), c = j0 + 16 * b + cc;
+                if (i < m && c < m)
+                    gb[i * m + c] = cx<T>{-cr[a][b][v], -ci[a][b][v]};
+            }
+}
+
+} // namespace crs

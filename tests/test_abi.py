@@ -31,7 +31,7 @@ def test_plan_validation_host_only():
             _lib.Plan(*bad)
         assert e.value.code == _lib.EINVAL
     with pytest.raises(_lib.CrsolveError) as e:
-        _lib.Plan([8], [65], [1])
+        _lib.Plan([8], [257], [1])
     assert e.value.code == _lib.EUNSUPPORTED
     with pytest.raises(_lib.CrsolveError) as e:
         _lib.Plan([8], [4], [1], dtype=_lib.C64, schedule=_lib.SCHED_PCR)

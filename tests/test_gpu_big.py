@@ -1,0 +1,215 @@
+"""Parity of the tiled kernels for block sizes 64 < m <= 256 (GPU).
+
+Same bar as the small-block parity tests: flags bit-exact with the oracle,
+solutions within 1e-11 (FP64) of the oracle's, residual <= 1e-12; block
+sizes that are not multiples of 16 exercise the padded last tile, and the
+shapes span several levels, odd block counts and k above one strip.  The
+block 2D Poisson workload (N = 4096, m = 256, k = 1) is checked at full size
+against its closed-form eigen-solution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_00370_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32 = 2e-4
+RES64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def tdev(cuda_ok):
+    import torch
+    from paper_1807_00370_amd import _lib
+    _lib.load()
+    return torch, torch.device("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _info(rec):
+    return dict(status=int(rec["status"]), level=int(rec["level"]), block=int(rec["block"]))
+
+
+def _solve(torch, dev, s, schedule="cr", dtype=None):
+    from paper_1807_00370_amd.solver import Solver
+    dt = dtype or torch.complex128
+    A, B, y = (torch.from_numpy(np.ascontiguousarray(v)).to(dev).to(dt) for v in (s.A, s.B, s.y))
+    sol = Solver([s.N], [s.m], [s.k], dtype=dt, schedule=schedule, device=dev)
+    x = sol.factor_solve(A, B, y)
+    torch.cuda.synchronize()
+    return x.cpu().numpy().astype(np.complex128), _info(sol.info_host()[0])
+
+
+BIG = [(5, 65, 3), (33, 80, 1), (64, 100, 7), (17, 128, 16), (9, 256, 1), (12, 200, 33),
+       (1, 96, 2), (2, 72, 20), (40, 144, 5)]
+
+
+@pytest.mark.parametrize("N,m,k", BIG)
+def test_big_cr_matches_oracle(tdev, N, m, k):
+    torch, dev = tdev
+    print("case big cr N=%d m=%d k=%d" % (N, m, k), flush=True)
+    s = W.random_hpd(N, m, k, 9100 + N + 7 * m + k)
+    x, info = _solve(torch, dev, s)
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert info == io
+    assert _rel(x, xo) <= TOL64
+    assert oracle.rel_residual(s.A, s.B, x, s.y) <= RES64
+
+
+@pytest.mark.parametrize("N,m,k", [(9, 80, 2), (16, 128, 1), (3, 256, 4)])
+def test_big_pcr_matches_oracle(tdev, N, m, k):
+    torch, dev = tdev
+    print("case big pcr N=%d m=%d k=%d" % (N, m, k), flush=True)
+    s = W.random_hpd(N, m, k, 9200 + N + m)
+    x, info = _solve(torch, dev, s, schedule="pcr")
+    xo, io = oracle.solve_pcr(s.A, s.B, s.y)
+    assert info == io
+    assert _rel(x, xo) <= TOL64
+    assert oracle.rel_residual(s.A, s.B, x, s.y) <= RES64
+
+
+def test_big_complex64(tdev):
+    torch, dev = tdev
+    s = W.random_hpd(40, 96, 4, 9300)
+    x, info = _solve(torch, dev, s, dtype=torch.complex64)
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert info == io
+    assert _rel(x, xo) <= TOL32
+
+
+def test_big_factor_then_solve_bitwise(tdev):
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import Solver
+    s = W.random_hpd(21, 112, 3, 9400)
+    A, B, y = (torch.from_numpy(v).to(dev) for v in (s.A, s.B, s.y))
+    sol = Solver([s.N], [s.m], [s.k], device=dev)
+    sol.factor(A, B)
+    x1 = sol.solve(y).cpu().numpy()
+    xf = sol.factor_solve(A, B, y).cpu().numpy()
+    assert np.array_equal(xf, x1)
+    xo, _ = oracle.solve_cr(s.A, s.B, s.y)
+    assert _rel(x1, xo) <= TOL64
+
+
+def test_big_indefinite_flags(tdev):
+    """The shifted twin breaks down at level 0; 80 decoupled copies of the
+    scalar system A_j = 1, B_j = 0.55 (positive blocks, indefinite matrix)
+    break down at level 2, original block 4 -- both schedules."""
+    torch, dev = tdev
+    t = W.random_hpd(20, 80, 2, 9500, shift_scale=2.0)
+    xt, it = _solve(torch, dev, t)
+    _, iot = oracle.solve_cr(t.A, t.B, t.y)
+    assert it == iot and it["status"] == 1
+    assert np.isnan(xt).all()
+    N, m = 64, 80
+    A = np.broadcast_to(np.eye(m), (N, m, m)).astype(np.complex128)
+    B = np.broadcast_to(0.55 * np.eye(m), (N - 1, m, m)).astype(np.complex128)
+    y = np.ones((N, m, 1), np.complex128)
+    s = W.System(np.ascontiguousarray(A), np.ascontiguousarray(B), y)
+    for sched, ref in (("cr", oracle.solve_cr), ("pcr", oracle.solve_pcr)):
+        x, info = _solve(torch, dev, s, schedule=sched)
+        _, io = ref(s.A, s.B, s.y)
+        assert info == io == dict(status=1, level=2, block=4)
+        assert np.isnan(x).all()
+
+
+def test_big_ragged_batch_with_small_blocks(tdev):
+    """Tiled and small-block classes in one plan, one launch per level and
+    class; each system equals its own oracle solve."""
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import Solver
+    shapes = [(30, 96, 3), (64, 32, 16), (17, 256, 1), (100, 8, 4), (9, 130, 17)]
+    systems = [W.random_hpd(N, m, k, 9600 + i) for i, (N, m, k) in enumerate(shapes)]
+    A = np.concatenate([s.A.ravel() for s in systems])
+    B = np.concatenate([s.B.ravel() for s in systems])
+    y = np.concatenate([s.y.ravel() for s in systems])
+    sol = Solver([s.N for s in systems], [s.m for s in systems], [s.k for s in systems],
+                 device=dev)
+    At, Bt, yt = (torch.from_numpy(v).to(dev) for v in (A, B, y))
+    x = sol.factor_solve(At, Bt, yt).cpu().numpy()
+    off = 0
+    for i, s in enumerate(systems):
+        xs = x[off:off + s.y.size].reshape(s.y.shape)
+        off += s.y.size
+        xo, io = oracle.solve_cr(s.A, s.B, s.y)
+        assert _info(sol.info_host()[i]) == io
+        assert _rel(xs, xo) <= TOL64, i
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_big_backward_matches_oracle(tdev, dt):
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import cr_solve
+    dtype = torch.complex128 if dt == "c128" else torch.complex64
+    s = W.random_hpd(11, 90, 5, 9700, with_W=True)
+    A, B, y, Wt = (torch.from_numpy(v).to(dev).to(dtype) for v in (s.A, s.B, s.y, s.W))
+    for t in (A, B, y):
+        t.requires_grad_(True)
+    x = cr_solve(A, B, y)
+    (Wt.conj() * x).real.sum().backward()
+    xo, _ = oracle.solve_cr(s.A, s.B, s.y)
+    lam, _ = oracle.solve_cr(s.A, s.B, s.W)
+    gA, gB = oracle.backward(xo, lam)
+    tol = TOL64 * 10 if dt == "c128" else TOL32 * 5
+    assert _rel(A.grad.cpu().numpy(), gA) <= tol
+    assert _rel(B.grad.cpu().numpy(), gB) <= tol
+    assert _rel(y.grad.cpu().numpy(), lam) <= tol
+
+
+def test_big_refine(tdev):
+    """FP32 tiled levels, FP64 tail, FP64 residual refinement to 1e-12."""
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import Solver
+    s = W.random_hpd(64, 128, 4, 9800)
+    A, B, y = (torch.from_numpy(v).to(dev) for v in (s.A, s.B, s.y))
+    sol = Solver([s.N], [s.m], [s.k], precision="fp32_refine", device=dev, rtol=1e-12,
+                 max_refine=30, fp64_tail_blocks=4)
+    x = sol.factor_solve(A, B, y).cpu().numpy()
+    rec = sol.info_host()[0]
+    assert int(rec["status"]) == 0 and int(rec["fp64_fallback"]) == 0
+    res = oracle.rel_residual(s.A, s.B, x, s.y)
+    assert res <= RES64
+    assert abs(float(rec["rel_residual"]) - res) <= 0.1 * res + 1e-16
+    xo, _ = oracle.solve_cr(s.A, s.B, s.y)
+    assert _rel(x, xo) <= TOL64
+
+
+def test_poisson_small_matches_oracle(tdev):
+    """Block 2D Poisson, N = 64, m = 256: oracle and closed form."""
+    torch, dev = tdev
+    s = W.poisson(64, 256, p=2, q=3)
+    x, info = _solve(torch, dev, s)
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert info == io == dict(status=0, level=-1, block=-1)
+    assert _rel(x, xo) <= TOL64
+    assert _rel(x, s.y / s.meta["lam"]) <= TOL64
+
+
+def test_poisson_full_size_closed_form(tdev):
+    """N = 4096, m = 256, k = 1, complex128 (the Poisson workload): the
+    solution is y / lambda.  With y the lowest eigenvector,
+    ||A|| ||x|| / ||y|| = lambda_max / lambda_min ~ 5.3e4, so even the
+    correctly rounded exact solution fl(y / lambda) has a relative residual
+    of about u * 5.3e4 ~ 6e-12: 1e-12 is below the FP64 floor for this
+    right-hand side.  The bounds are the backward-stable ones, c u kappa with
+    c = 16 for the residual and for the forward error (kappa ~ 5.3e4)."""
+    torch, dev = tdev
+    print("case poisson N=4096 m=256 k=1", flush=True)
+    s = W.poisson(W.POISSON["N"], W.POISSON["m"])
+    x, info = _solve(torch, dev, s)
+    assert info == dict(status=0, level=-1, block=-1)
+    lam = s.meta["lam"]
+    kappa = 8.0 / lam  # Gershgorin bound on lambda_max over the smallest eigenvalue
+    u = np.finfo(np.float64).eps / 2
+    x_exact = s.y / lam
+    assert _rel(x, x_exact) <= 16 * u * kappa
+    res = oracle.rel_residual(s.A, s.B, x, s.y)
+    res_rounded_exact = oracle.rel_residual(s.A, s.B, x_exact, s.y)
+    print("residual %.3e, of the rounded exact solution %.3e" % (res, res_rounded_exact))
+    assert res <= 16 * u * kappa

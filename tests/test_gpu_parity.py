@@ -223,7 +223,7 @@ def test_invalid_arguments(torch_dev):
         _lib.Plan([0], [4], [1])
     assert e.value.code == _lib.EINVAL
     with pytest.raises(_lib.CrsolveError) as e:
-        _lib.Plan([8], [65], [1])
+        _lib.Plan([8], [257], [1])
     assert e.value.code == _lib.EUNSUPPORTED
     with pytest.raises(_lib.CrsolveError) as e:
         _lib.Plan([8], [4], [1], dtype=_lib.C64, schedule=_lib.SCHED_PCR)
