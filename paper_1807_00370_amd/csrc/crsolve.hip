@@ -235,7 +235,11 @@ struct Disp {
                      const void* iny, void* W, unsigned long long* flags, int mat, int rhs,
                      hipStream_t st, int variant)
     {
-        if (MT <= 32 && variant == 0) {
+        if ((MT == 16 || MT == 32) && variant == 0) {
+            hipLaunchKernelGGL((crs::k_elim_mf<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                               (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+        } else if (MT <= 32 && variant == 0) {
             hipLaunchKernelGGL((crs::k_elim_w<T, MT <= 32 ? MT : 32>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);

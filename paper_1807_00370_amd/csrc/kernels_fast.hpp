@@ -342,6 +342,238 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
     }
 }
 
+// ---------------------------------------------------------------- k_elim_mf
+
+// Elimination for block sizes 8 < m <= 32 with the forward substitutions on
+// MFMA.  After the Cholesky (as in k_elim_w) the inverses D_I = L_II^{-1} of
+// the 16 x 16 diagonal tiles are formed, and each 16-column strip G of
+// [B_p^H | B_{p-d} | y_p] is solved tile by tile, X_0 = D_0 G_0 and
+// X_1 = D_1 (G_1 - L_10 X_0): register v of a lane's accumulator holds row
+// MF::row(kr, v) of its column, which is the right operand of contraction
+// step v when the left operand supplies column MF::row(kr, v), so the
+// products chain through the accumulators.  Right-hand sides are read from
+// memory straight into that layout, the first strip before the Cholesky and
+// each next strip while the current one is solved.
+template <class T, int MT>
+__global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs, int nseg,
+                                                   int64_t total, const cx<T>* __restrict__ inA,
+                                                   const cx<T>* __restrict__ inB,
+                                                   const cx<T>* __restrict__ iny,
+                                                   cx<T>* __restrict__ W,
+                                                   unsigned long long* __restrict__ flags,
+                                                   int with_mat, int with_rhs)
+{
+    static_assert(MT == 16 || MT == 32, "one or two 16-row tiles");
+    using v4 = typename MF<T>::v4;
+    constexpr int S = MT / 16;
+    constexpr int NP = MT * (MT + 1) / 2;
+    constexpr int NS = NP > S * 256 ? NP : S * 256;
+    __shared__ cx<T> sL[NS]; // packed L, later the D tiles
+    __shared__ int sFail;
+    const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
+    const int64_t w = blockIdx.x;
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int p = s.e0 + (int)t * s.es;
+    const int m = s.m, k = s.k, d = s.d;
+    const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
+    const int np = m * (m + 1) / 2;
+    const bool hasPrev = p - d >= 0, hasNext = p + d < s.n;
+    if ((flags[s.sys] >> 40) < (unsigned long long)s.level)
+        return; // broke down at an earlier level: nothing left to do
+    cx<T>* Lg = W + s.oL + t * mm;
+
+    // strips: S of B_p^H (into P), S of B_{p-d} (into Q), ceil(k / 16) of y_p
+    const int nP = (with_mat && hasNext) ? S : 0;
+    const int nQ = (with_mat && hasPrev) ? S : 0;
+    const int nst = nP + nQ + (with_rhs ? (k + 15) / 16 : 0);
+    const cx<T>* Bp = inB + s.oB + (int64_t)p * mm;
+    const cx<T>* Bq = inB + s.oB + (int64_t)(p - d) * mm;
+    const cx<T>* yp = iny + s.oy + (int64_t)p * mk;
+    // element (r, c) of strip st's source is base[r * sr + c * sc], conjugated
+    // for B_p^H
+#define CRS_LOAD_STRIP(st, g)                                                                      \
+    do {                                                                                           \
+        const int src_ = (st) < nP ? 0 : ((st) < nP + nQ ? 1 : 2);                                 \
+        const int c_ = 16 * (src_ == 0 ? (st) : (src_ == 1 ? (st) - nP : (st) - nP - nQ)) + cc;    \
+        const cx<T>* base_ = src_ == 0 ? Bp : (src_ == 1 ? Bq : yp);                               \
+        const int sr_ = src_ == 0 ? 1 : (src_ == 1 ? m : k), sc_ = src_ == 0 ? m : 1;               \
+        const bool okc_ = c_ < (src_ == 2 ? k : m);                                                \
+        const T cj_ = src_ == 0 ? T(-1) : T(1);                                                    \
+        const cx<T>* col_ = base_ + (okc_ ? c_ : 0) * sc_;                                         \
+        _Pragma("unroll") for (int I_ = 0; I_ < S; ++I_)                                           \
+            _Pragma("unroll") for (int v_ = 0; v_ < 4; ++v_)                                       \
+            {                                                                                      \
+                const int r_ = 16 * I_ + MF<T>::row(kr, v_);                                       \
+                cx<T> x_ = czero<T>();                                                             \
+                if (okc_ && r_ < m)                                                                \
+                    x_ = col_[r_ * sr_];                                                           \
+                g[I_][v_] = cx<T>{x_.r, cj_ * x_.i};                                               \
+            }                                                                                      \
+    } while (0)
+    cx<T> gn[S][4];
+
+    if (with_mat) {
+        const cx<T>* Ap = inA + s.oA + (int64_t)p * mm;
+        for (int e = lane; e < np; e += 64) {
+            const int r = tri_row(e), c = e - r * (r + 1) / 2;
+            sL[e] = Ap[r * m + c];
+        }
+        __syncthreads();
+        // left-looking Cholesky, one row per lane (as in k_elim_w)
+        cx<T> a[MT];
+        const int rl = lane < m ? lane : 0;
+#pragma unroll
+        for (int u = 0; u < MT; ++u)
+            a[u] = (u <= rl) ? sL[rl * (rl + 1) / 2 + u] : czero<T>();
+        __syncthreads();
+        bool fail = false;
+#pragma unroll
+        for (int c = 0; c < MT; ++c) {
+            if (c < m) {
+                cx<T> s0 = czero<T>(), s1 = czero<T>();
+                // dot product in chunks of 16 terms (bounds the LDS reads in
+                // flight next to the 2 MT registers of the row)
+#pragma unroll
+                for (int u = 0; u + 1 < c; u += 2) {
+                    msub_cb(s0, a[u], sL[c * (c + 1) / 2 + u]);
+                    msub_cb(s1, a[u + 1], sL[c * (c + 1) / 2 + u + 1]);
+                    if ((u & 15) == 14)
+                        __builtin_amdgcn_sched_barrier(0);
+                }
+                if (c & 1)
+                    msub_cb(s0, a[c - 1], sL[c * (c + 1) / 2 + c - 1]);
+                const cx<T> v{a[c].r + s0.r + s1.r, a[c].i + s0.i + s1.i};
+                const T dg = __shfl(v.r, c);
+                const T inv = rsqrt_nr(dg);
+                const T sq = dg * inv;
+                fail |= !(dg > T(0));
+                if (lane == c)
+                    a[c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
+                else
+                    a[c] = cx<T>{v.r * inv, v.i * inv};
+                if (lane >= c && lane < m)
+                    sL[lane * (lane + 1) / 2 + c] = a[c];
+                __syncthreads();
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (lane == 0)
+            sFail = fail;
+        if (lane == 0 && sFail)
+            atomicMin(&flags[s.sys], fail_key(s.level, s.ob0 + s.obs * p));
+        for (int e = lane; e < np; e += 64)
+            Lg[e] = sL[e];
+    } else {
+        for (int e = lane; e < np; e += 64)
+            sL[e] = Lg[e];
+    }
+    __syncthreads();
+
+    // left operands: L_10 and the D tiles (lane j < 16 S forms column j & 15
+    // of D_{j / 16} by forward substitution; padded rows are identity rows)
+    cx<T> aL[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = 16 + cc, u = MF<T>::row(kr, v);
+        aL[v] = (S == 2 && i < m) ? sL[i * (i + 1) / 2 + u] : czero<T>();
+    }
+    const int I0 = (lane >> 4) < S ? (lane >> 4) : 0, jj = lane & 15;
+    cx<T> z[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int gq = 16 * I0 + q;
+        cx<T> v = q == jj ? cx<T>{T(1), T(0)} : czero<T>();
+        if (gq < m) {
+            const int base = gq * (gq + 1) / 2 + 16 * I0;
+#pragma unroll
+            for (int u = 0; u < q; ++u)
+                msub(v, sL[base + u], z[u]);
+            const T iq = sL[base + q].i;
+            v = cx<T>{v.r * iq, v.i * iq};
+        }
+        z[q] = v;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads(); // every read of L in LDS is done
+    if (lane < 16 * S) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            sL[I0 * 256 + q * 16 + jj] = z[q];
+    }
+    __syncthreads();
+    cx<T> aD[S][4];
+#pragma unroll
+    for (int I = 0; I < S; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            aD[I][v] = sL[I * 256 + cc * 16 + MF<T>::row(kr, v)];
+
+    if (nst > 0)
+        CRS_LOAD_STRIP(0, gn);
+#pragma unroll 1
+    for (int st = 0; st < nst; ++st) {
+        cx<T> g[S][4];
+#pragma unroll
+        for (int I = 0; I < S; ++I)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                g[I][v] = gn[I][v];
+        if (st + 1 < nst)
+            CRS_LOAD_STRIP(st + 1, gn);
+        // X_0 = D_0 G_0
+        v4 x0r = {0, 0, 0, 0}, x0i = {0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const cx<T> a = aD[0][v], b = g[0][v];
+            x0r = MF<T>::mma(a.r, b.r, x0r);
+            x0r = MF<T>::mma(-a.i, b.i, x0r);
+            x0i = MF<T>::mma(a.r, b.i, x0i);
+            x0i = MF<T>::mma(a.i, b.r, x0i);
+        }
+        v4 x1r = {0, 0, 0, 0}, x1i = {0, 0, 0, 0};
+        if (S == 2) {
+            // T = L_10 X_0, then X_1 = D_1 (G_1 - T)
+            v4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const cx<T> a = aL[v];
+                tr = MF<T>::mma(a.r, x0r[v], tr);
+                tr = MF<T>::mma(-a.i, x0i[v], tr);
+                ti = MF<T>::mma(a.r, x0i[v], ti);
+                ti = MF<T>::mma(a.i, x0r[v], ti);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const cx<T> a = aD[S - 1][v];
+                const T br = g[S - 1][v].r - tr[v], bi = g[S - 1][v].i - ti[v];
+                x1r = MF<T>::mma(a.r, br, x1r);
+                x1r = MF<T>::mma(-a.i, bi, x1r);
+                x1i = MF<T>::mma(a.r, bi, x1i);
+                x1i = MF<T>::mma(a.i, br, x1i);
+            }
+        }
+        const int src = st < nP ? 0 : (st < nP + nQ ? 1 : 2);
+        const int c = 16 * (src == 0 ? st : (src == 1 ? st - nP : st - nP - nQ)) + cc;
+        const int ld = src == 2 ? k : m;
+        cx<T>* out = src == 0 ? W + s.oP + t * mm : (src == 1 ? W + s.oQ + t * mm : W + s.og + t * mk);
+        if (c < ld) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r0 = MF<T>::row(kr, v);
+                if (r0 < m)
+                    out[r0 * ld + c] = cx<T>{x0r[v], x0i[v]};
+                if (S == 2 && 16 + r0 < m)
+                    out[(16 + r0) * ld + c] = cx<T>{x1r[v], x1i[v]};
+            }
+        }
+    }
+}
+
+#undef CRS_LOAD_STRIP
+
 // --------------------------------------------------------------- k_reduce_m
 
 // MFMA operand tile: 16 columns [c0, c0 + 16) of a row-major matrix with
