@@ -38,6 +38,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -131,14 +133,49 @@ def step_model(form, N, m, k, iters=0):
     return tot
 
 
-def cpu_baseline(s, budget_s: float, what: str = "full workload"):
-    """The oracle's one-sided reduction on the host cores (at least one solve,
-    repeated until the budget is spent)."""
+def pcr_model(N, m, k):
+    """Algorithm 1 in place: at level l (distance d = 2^l) every block is
+    eliminated and every block is reduced; the last level only factors and
+    solves its uncoupled blocks.  Per-kernel algorithmic [bytes, flops], FP64."""
+    mm, mk, T, s = m * m, m * k, m * (m + 1) // 2, 16
+    tot = {"k_elim": [0.0, 0.0], "k_reduce": [0.0, 0.0], "k_back": [0.0, 0.0]}
+    D = 0
+    while (1 << D) < N:
+        D += 1
+    for lvl in range(D + 1):
+        d = 1 << lvl
+        nb = max(N - d, 0)       # blocks with a neighbour at distance d on one side
+        nf = max(N - 2 * d, 0)   # kept blocks with a reduced off-diagonal block
+        tot["k_elim"][0] += (N * (2 * T + 2 * mk) + 2 * nb * 2 * mm) * s
+        tot["k_elim"][1] += 8 * (N * mm * m / 6 + 2 * nb * mm * m / 2 + N * mk * m / 2)
+        if lvl < D:
+            tot["k_reduce"][0] += (N * (2 * T + 2 * mk) + 2 * nb * (mm + mk) + nf * 2 * mm) * s
+            tot["k_reduce"][1] += 8 * (2 * nb * mm * m / 2 + nf * mm * m + 2 * nb * mk * m)
+        else:
+            tot["k_back"][0] += N * (T + 2 * mk) * s
+            tot["k_back"][1] += 8 * N * mk * m / 2
+    return tot
+
+
+def adjoint_model(N, m, k, s):
+    """Backward pass: the rhs-only levels and back substitution for lam, then
+    the gradient blocks (read lam_j, x_j, lam_{j+1}, x_{j+1}; write gA_j, gB_j)."""
+    tot = pass_model(N, m, k, lambda n: s, False, True)
+    mm, mk = m * m, m * k
+    add(tot, {"k_grad": [(N * (4 * mk + mm) + (N - 1) * mm) * s,
+                         8 * (N * mm * k + (N - 1) * 2 * mm * k)]})
+    return tot
+
+
+def cpu_baseline(s, budget_s: float, what: str = "full workload", solver: str = "cr"):
+    """The oracle's one-sided reduction (or Algorithm 1) on the host cores (at
+    least one solve, repeated until the budget is spent)."""
     import oracle
     oracle.build(force=False)
+    fn = oracle.solve_pcr if solver == "pcr" else oracle.solve_cr
     reps, t0 = 0, time.perf_counter()
     while True:
-        x, info = oracle.solve_cr(s.A, s.B, s.y)
+        x, info = fn(s.A, s.B, s.y)
         reps += 1
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 8:
@@ -146,8 +183,9 @@ def cpu_baseline(s, budget_s: float, what: str = "full workload"):
     assert info["status"] == 0
     return {"value": s.N * reps / el, "unit": "block-rows/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "%s (N=%d, m=%d, k=%d, complex128), FP64 one-sided cyclic "
-                      "reduction, %d solve(s) in %.1f s" % (what, s.N, s.m, s.k, reps, el)}
+            "sample": "%s (N=%d, m=%d, k=%d, complex128), FP64 %s, %d solve(s) in %.1f s" % (
+                what, s.N, s.m, s.k, "Algorithm 1" if solver == "pcr" else
+                "one-sided cyclic reduction", reps, el)}
 
 
 def timed_steps(torch, sol, A, B, y, x, steps, warmup):
@@ -228,6 +266,176 @@ def roofline(per_step, mod, prec_f64, form="fp64"):
     return r
 
 
+def time_steps(torch, step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def kernel_times(torch, sol, step, steps):
+    sol.timing(True)
+    for _ in range(steps):
+        step()
+    kt = sol.timing_read()
+    sol.timing(False)
+    torch.cuda.synchronize()
+    return {kn: (cnt / steps, tot / steps) for kn, (cnt, tot) in kt.items()}
+
+
+def emit(args, value, ms, dtype, config, forms, roof, cpu, model=None):
+    out = {"metric": METRIC, "value": value, "unit": "block-rows/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": config}
+    if model is not None:
+        out["step_model"] = model
+    out.update({"roofline": roof, "forms": forms, "cpu_baseline": cpu})
+    print(json.dumps(out), flush=True)
+
+
+def run_diff(args, torch, W, dev):
+    """Differentiation workload: forward solve plus the adjoint (lam = A^{-1}
+    dL/dx from the stored factors, gradient blocks) for L = sum_j Re tr(W_j^H
+    x_j), so dL/dx = W; N=16384, m=64, k=32 in complex128 and complex64."""
+    import oracle
+    from paper_1807_00370_amd.solver import Solver
+    N, m, k = W.DIFF["N"], W.DIFF["m"], W.DIFF["k"]
+    s = W.random_hpd(N, m, k, W.config_seed(4), with_W=True)
+    forms = {}
+    for name, dt, es in (("c128", torch.complex128, 16), ("c64", torch.complex64, 8)):
+        A, B, y, gx = (torch.from_numpy(v).to(dev).to(dt) for v in (s.A, s.B, s.y, s.W))
+        x = torch.empty_like(y)
+        sol = Solver([N], [m], [k], dtype=dt, device=dev)
+
+        def step():
+            sol.factor_solve(A, B, y, x)
+            return sol.backward(x, gx)
+
+        ms = time_steps(torch, step, args.steps, args.warmup)
+        per_step = kernel_times(torch, sol, step, args.steps)
+        info = sol.info_host()[0]
+        if info["status"] != 0:
+            raise SystemExit("diff %s: factorization failed" % name)
+        mod = add(pass_model(N, m, k, lambda n: es, True, True), adjoint_model(N, m, k, es))
+        forms[name] = {"ms_per_step": ms, "value": N / (ms * 1e-3),
+                       "kernel_ms_per_step": {kn: round(v[1], 4) for kn, v in per_step.items()},
+                       "roofline": roofline(per_step, mod, es == 16, "diff_" + name),
+                       "model_bytes": sum(v[0] for v in mod.values()),
+                       "model_flops": sum(v[1] for v in mod.values())}
+        if name == "c128":
+            forms[name]["rel_residual"] = sol.residual(A, B, x, y)[0]
+        print("diff %s: %.3f ms/step (forward + adjoint), %s" % (
+            name, ms, json.dumps(forms[name]["kernel_ms_per_step"])), file=sys.stderr, flush=True)
+        del sol, A, B, y, gx, x
+        torch.cuda.synchronize()
+    cpu = None
+    if not args.no_cpu_baseline:
+        oracle.build(force=False)
+        smp = W.random_hpd(1024, m, k, W.config_seed(4, 1), with_W=True)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            xo, _ = oracle.solve_cr(smp.A, smp.B, smp.y)
+            lam, _ = oracle.solve_cr(smp.A, smp.B, smp.W)
+            oracle.backward(xo, lam)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_budget or reps >= 8:
+                break
+        cpu = {"value": smp.N * reps / el, "unit": "block-rows/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": "N=1024 sample of the differentiation workload (m=%d, "
+               "k=%d, complex128): forward solve, adjoint solve and gradient blocks, %d time(s) "
+               "in %.1f s" % (m, k, reps, el)}
+    f = forms["c128"]
+    emit(args, f["value"], f["ms_per_step"], "c128",
+         {"workload": "differentiation: forward solve + adjoint of one HPD system, N=%d, m=%d, "
+                      "k=%d, complex128 (complex64 under forms)" % (N, m, k),
+          "N": N, "m": m, "k": k, "form": "c128"}, forms, f["roofline"], cpu)
+
+
+def run_batch(args, torch, W, dev):
+    """Batching workload: 512 independent systems of uneven N, m, k in one
+    plan (one launch per level, block-size class and precision), the launch
+    sequence replayed as a HIP graph; complex128 inputs solved by the
+    FP32 + FP64-refinement form (the stated form) and by the FP64 form."""
+    import oracle
+    from paper_1807_00370_amd.solver import Solver
+    t0 = time.perf_counter()
+    shapes = W.batch_shapes(W.BATCH_COUNT, W.config_seed(3), n_half_range=(128, args.batch_half_max))
+    # forked generator processes (no GPU use before this point), one per core up to 16
+    hA, hB, hy = W.batch_packed(shapes, W.config_seed(3), workers=min(16, os.cpu_count() or 1))
+    print("batch inputs generated in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    Ns, ms_, ks = [q[0] for q in shapes], [q[1] for q in shapes], [q[2] for q in shapes]
+    A, B, y = (torch.from_numpy(v).to(dev) for v in (hA, hB, hy))
+    del hA, hB, hy
+    x = torch.empty_like(y)
+    rows = sum(Ns)
+    forms = {}
+    for form in ("fp32_refine", "fp64"):
+        if form == "fp64":
+            sol = Solver(Ns, ms_, ks, device=dev)
+            tuning = sol.autotune(A, B, y)
+        else:
+            sol = Solver(Ns, ms_, ks, precision="fp32_refine", device=dev, rtol=RTOL,
+                         max_refine=30, fp64_tail_blocks=TAIL)
+            tuning = None
+        sol.set_graphs(True)
+        step = lambda: sol.factor_solve(A, B, y, x)
+        ms = time_steps(torch, step, args.steps, args.warmup)
+        sol.set_graphs(False)
+        per_step = kernel_times(torch, sol, step, args.steps)
+        info = sol.info_host()
+        if (info["status"] != 0).any():
+            raise SystemExit("batch %s: a factorization failed" % form)
+        rel = sol.residual(A, B, x, y)
+        mod = {}
+        for i, (N, m, k) in enumerate(zip(Ns, ms_, ks)):
+            add(mod, step_model(form, N, m, k, int(info["refine_iters"][i]) if form != "fp64" else 0))
+        forms[form] = {"ms_per_step": ms, "value": rows / (ms * 1e-3), "tuning": tuning,
+                       "max_rel_residual": float(np.max(rel)),
+                       "certified": bool(np.max(rel) <= RTOL),
+                       "max_refine_iters": int(np.max(info["refine_iters"])),
+                       "fp64_fallbacks": int(np.sum(info["fp64_fallback"])),
+                       "kernel_ms_per_step": {kn: round(v[1], 4) for kn, v in per_step.items()},
+                       "roofline": roofline(per_step, mod, form == "fp64", "batch_" + form),
+                       "model_bytes": sum(v[0] for v in mod.values()),
+                       "model_flops": sum(v[1] for v in mod.values())}
+        print("batch %s: %.3f ms/step, max rel residual %.2e, %s" % (
+            form, ms, np.max(rel), json.dumps(forms[form]["kernel_ms_per_step"])),
+            file=sys.stderr, flush=True)
+        del sol
+        torch.cuda.synchronize()
+    cpu = None
+    if not args.no_cpu_baseline:
+        oracle.build(force=False)
+        reps, done, t0 = 0, 0, time.perf_counter()
+        for q in W.batch_systems(shapes[:16], W.config_seed(3)):
+            oracle.solve_cr(q.A, q.B, q.y)
+            done += q.N
+            reps += 1
+            if time.perf_counter() - t0 >= args.cpu_budget:
+                break
+        el = time.perf_counter() - t0
+        cpu = {"value": done / el, "unit": "block-rows/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": "the first %d systems of the batch (%d block rows), "
+               "FP64 one-sided cyclic reduction, in %.1f s" % (reps, done, el)}
+    best = min((f for f in forms if forms[f]["certified"]), key=lambda f: forms[f]["ms_per_step"])
+    f = forms[best]
+    emit(args, f["value"], f["ms_per_step"], "c64+f64" if best != "fp64" else "c128",
+         {"workload": "batch of %d independent HPD systems, N = 2 U{128..%d}, m in {8,16,32,64}, "
+                      "k in {1,4,16}, complex128 inputs, %d block rows, solved to rel. residual "
+                      "<= 1e-12 (%s form, graph replay)" % (len(shapes), args.batch_half_max,
+                                                            rows, best),
+          "systems": len(shapes), "block_rows": rows, "form": best,
+          "n_half_range": [128, args.batch_half_max]}, forms, f["roofline"], cpu)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,7 +445,12 @@ def main():
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--forms", default="fp64,fp32_refine")
-    ap.add_argument("--workload", choices=("random", "poisson"), default="random",
+    ap.add_argument("--schedule", choices=("cr", "pcr"), default="cr",
+                    help="cr: one-sided reduction (default); pcr: Algorithm 1 as printed (fp64)")
+    ap.add_argument("--batch-half-max", type=int, default=512,
+                    help="batch workload: N = 2 U{128..this}; the stated workload has 4096, whose "
+                         "inputs (~94 GB) and FP64 fallback workspace exceed one GPU's HBM")
+    ap.add_argument("--workload", choices=("random", "poisson", "diff", "batch"), default="random",
                     help="random: the HPD generator at --N/--m/--k; poisson: the block 2D "
                          "Poisson system N=4096, m=256, k=1 with an eigenvector right-hand side")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -258,6 +471,10 @@ def main():
     from paper_1807_00370_amd.solver import Solver
 
     dev = torch.device("cuda:0")
+    if args.workload == "diff":
+        return run_diff(args, torch, W, dev)
+    if args.workload == "batch":
+        return run_batch(args, torch, W, dev)
     t0 = time.perf_counter()
     if args.workload == "poisson":
         s = W.poisson(W.POISSON["N"], W.POISSON["m"])
@@ -281,20 +498,24 @@ def main():
         del dst
 
     forms = {}
+    pcr = args.schedule == "pcr"
     for form in args.forms.split(","):
+        if pcr and form != "fp64":
+            continue  # Algorithm 1 runs in FP64 only
         if form == "fp64":
-            sol = Solver([s.N], [s.m], [s.k], dtype=torch.complex128, device=dev)
+            sol = Solver([s.N], [s.m], [s.k], dtype=torch.complex128, device=dev,
+                         schedule=args.schedule)
         else:
             sol = Solver([s.N], [s.m], [s.k], dtype=torch.complex128, precision="fp32_refine",
                          device=dev, rtol=rtol, max_refine=30, fp64_tail_blocks=TAIL)
-        tuning = sol.autotune(A, B, y) if form == "fp64" and s.m <= 64 else None
+        tuning = sol.autotune(A, B, y) if form == "fp64" and s.m <= 64 and not pcr else None
         ms, ms_eager, per_step = time_form(torch, sol, A, B, y, x, args.steps, args.warmup)
         info = sol.info_host()[0]
         if info["status"] != 0:
             raise SystemExit("%s: factorization failed: %s" % (form, info))
         rel = sol.residual(A, B, x, y)[0]
         iters = int(info["refine_iters"]) if form != "fp64" else 0
-        mod = step_model(form, s.N, s.m, s.k, iters)
+        mod = pcr_model(s.N, s.m, s.k) if pcr else step_model(form, s.N, s.m, s.k, iters)
         forms[form] = {
             "ms_per_step": ms,
             "ms_per_step_eager": ms_eager,
@@ -306,7 +527,7 @@ def main():
             "fp64_fallback": int(info["fp64_fallback"]) if form != "fp64" else 0,
             "kernel_ms_per_step": {kn: round(v[1], 4) for kn, v in per_step.items()},
             "kernel_launches_per_step": {kn: v[0] for kn, v in per_step.items()},
-            "roofline": roofline(per_step, mod, form == "fp64", form),
+            "roofline": roofline(per_step, mod, form == "fp64", ("pcr_" if pcr else "") + form),
             "model_bytes": sum(v[0] for v in mod.values()),
             "model_flops": sum(v[1] for v in mod.values()),
         }
@@ -326,6 +547,9 @@ def main():
         # reduction costs about the same at any N)
         cpu = cpu_baseline(W.poisson(256, W.POISSON["m"]), args.cpu_budget,
                            "sample of the Poisson workload")
+    elif pcr:
+        cpu = cpu_baseline(W.random_hpd(4096, s.m, s.k, W.config_seed(1, 1)), args.cpu_budget,
+                           "N=4096 sample of the workload, Algorithm 1", solver="pcr")
     else:
         cpu = cpu_baseline(s, args.cpu_budget)
     fb = forms[best]
@@ -345,12 +569,13 @@ def main():
         "dtype": "c128" if best == "fp64" else "c64+f64",
         "data": "synthetic",
         "config": {"workload": "%s, N=%d block rows, m=%d, k=%d, complex128 inputs, solved "
-                               "to rel. residual <= %.3g (one-sided block cyclic reduction, %s "
-                               "form)" % ("block 2D Poisson system, eigenvector right-hand side"
-                                          if args.workload == "poisson" else
-                                          "one HPD block-tridiagonal system", s.N, s.m, s.k,
-                                          rtol, best),
-                   "N": s.N, "m": s.m, "k": s.k, "form": best, "rtol": rtol},
+                               "to rel. residual <= %.3g (%s, %s form)" % (
+                                   "block 2D Poisson system, eigenvector right-hand side"
+                                   if args.workload == "poisson" else
+                                   "one HPD block-tridiagonal system", s.N, s.m, s.k, rtol,
+                                   "Algorithm 1 in place" if pcr else
+                                   "one-sided block cyclic reduction", best),
+                   "schedule": args.schedule, "N": s.N, "m": s.m, "k": s.k, "form": best, "rtol": rtol},
         "step_model": {"bytes": fb["model_bytes"], "flops": fb["model_flops"],
                        "roofline_ms": model_ms, "frac_of_step_roofline": model_ms / fb["ms_per_step"]},
         "roofline": fb["roofline"],

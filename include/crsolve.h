@@ -187,9 +187,13 @@ int crsolve_set_graphs(crsolve_plan *plan, int enable);
  * times, on the given data, the two kernel variants of each level role --
  * one-wave/MFMA kernels and work-group kernels -- for the elimination, the
  * reduced-system formation and the back substitution, and keeps the faster
- * one (synchronizes; overwrites x and the workspace).  The choice is returned
- * as a short text (cap bytes, NUL-terminated) that crsolve_set_tuning applies
- * to another plan, e.g. from a cache file.  NATIVE plans only. */
+ * one (synchronizes; overwrites x and the workspace).  Blocks above 32 have
+ * one elimination and one back-substitution kernel (tiled) and two variants
+ * of the reduced-system formation (tiled, or one wave per block), so only
+ * that role is tuned for them.  The choice is returned as a short text (cap
+ * bytes, NUL-terminated), one token "r<role>c<class>f<fp64>=<variant>;" per
+ * tuned role, that crsolve_set_tuning applies to another plan, e.g. from a
+ * cache file.  NATIVE plans only. */
 int crsolve_autotune(crsolve_plan *plan, const void *A, const void *B, const void *y, void *ws,
                      size_t ws_bytes, void *x, void *stream, char *choice, size_t cap);
 int crsolve_set_tuning(crsolve_plan *plan, const char *choice);

@@ -40,7 +40,11 @@ namespace {
 constexpr int kNT = 256;
 constexpr int kNumCls = 6;
 constexpr int kClsM[kNumCls] = {4, 8, 16, 32, 64, 256};
-constexpr int kBig = 5; // tiled kernels (kernels_big.hpp) for 64 < m <= 256
+constexpr int kBig = 5; // block sizes 64 < m <= 256
+// Classes whose elimination, back substitution and gradient run on the tiled
+// kernels of kernels_big.hpp (full m x m L slots plus inverse diagonal tiles);
+// their reduced-system step takes the tiled kernel as variant 0.
+bool tiled(int cls) { return cls >= 4; }
 constexpr size_t kAlign = 256;
 constexpr int kMaxGrid = 1 << 16; // work-group kernels loop grid-stride above this grid
 
@@ -259,7 +263,7 @@ struct Disp {
             hipLaunchKernelGGL((crs::k_reduce_m<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
-        } else if (MT == 64 && variant == 0) {
+        } else if (MT == 64) {
             hipLaunchKernelGGL((crs::k_reduce_t<T, 64>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
@@ -352,7 +356,7 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
     const void* inA = L.userAB ? A : c.ws;
     const void* inB = L.userAB ? B : c.ws;
     const void* iny = L.userY ? y : c.ws;
-    if (L.cls == kBig) {
+    if (tiled(L.cls)) {
         const BigDims b = big_dims(c.p, L);
         if (mat) {
             Timed tm(c.p, KID_POTRF, c.st, L.cls, L.f64);
@@ -382,7 +386,8 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
     const void* inA = L.userAB ? A : c.ws;
     const void* iny = L.userY ? y : c.ws;
     Timed tm(c.p, KID_REDUCE, c.st, L.cls, L.f64);
-    if (L.cls == kBig) {
+    const int v = c.p->var[1][L.cls][L.f64];
+    if (L.cls == kBig || (tiled(L.cls) && v == 0)) {
         const BigDims b = big_dims(c.p, L);
         const int nt = (mat ? b.T32 * (b.T32 + 1) / 2 + b.T32 * b.T32 : 0) + (rhs ? b.T32 * b.K32 : 0);
         if (nt > 0)
@@ -391,7 +396,6 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
                                (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
         return;
     }
-    const int v = c.p->var[1][L.cls][L.f64];
 #define CALL(MT) Disp<T>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st, v)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
@@ -402,7 +406,7 @@ void run_back(const Ctx& c, const Launch& L, void* x)
 {
     void* X = L.userX ? x : c.ws;
     Timed tm(c.p, KID_BACK, c.st, L.cls, L.f64);
-    if (L.cls == kBig) {
+    if (tiled(L.cls)) {
         const BigDims b = big_dims(c.p, L);
         hipLaunchKernelGGL((crs::k_back_big<T>), dim3(grid8(L.total * b.K16)), dim3(64), 0, c.st,
                            c.dsegs + L.seg0, L.nseg, L.total, b.K16, (const cx<T>*)c.ws, (cx<T>*)X,
@@ -419,7 +423,7 @@ template <class T>
 void run_grad(const Ctx& c, const Launch& L, const void* x, const void* lam, void* gA, void* gB)
 {
     Timed tm(c.p, KID_GRAD, c.st);
-    if (L.cls == kBig) {
+    if (tiled(L.cls)) {
         const BigDims b = big_dims(c.p, L);
         hipLaunchKernelGGL((crs::k_grad_big<T>), dim3(grid8(L.total * b.T32 * b.T32)), dim3(64), 0,
                            c.st, c.dsegs + L.seg0, L.nseg, L.total, b.T32 * b.T32, (const cx<T>*)x,
@@ -632,7 +636,7 @@ int build_plan(crsolve_plan* p)
                 v.oQ = a.take(v.ne * mm, es);
                 v.oAo = a.take(v.nk * mm, es);
                 v.oBo = a.take(std::max(v.nk - 1, 0) * mm, es);
-                if (p->cls[s] == kBig)
+                if (tiled(p->cls[s]))
                     v.oD = a.take(v.ne * dtiles, es);
             }
             for (size_t l = 0; l < L.size(); ++l) {
@@ -702,7 +706,7 @@ int build_plan(crsolve_plan* p)
             const size_t es = e64;
             int64_t oL = a.take(N * mm, es), oP = a.take(N * mm, es), oQ = a.take(N * mm, es),
                     og = a.take(N * mk, es);
-            const int64_t oD = p->cls[s] == kBig ? a.take(N * dtiles, es) : 0;
+            const int64_t oD = tiled(p->cls[s]) ? a.take(N * dtiles, es) : 0;
             int64_t bA[2], bB[2], by[2];
             for (int b = 0; b < 2; ++b) {
                 bA[b] = a.take(N * mm, es);
@@ -1470,9 +1474,11 @@ int crsolve_autotune(crsolve_plan* p, const void* A, const void* B, const void* 
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < kNumCls; ++c)
             for (int f = 0; f < 2; ++f) {
-                const int v = (seen[r][c][f] && t[1][r][c][f] < t[0][r][c][f]) ? 1 : 0;
+                // tiled classes have one elimination and one back-substitution kernel
+                const bool tuned = seen[r][c][f] && !(tiled(c) && r != 1);
+                const int v = (tuned && t[1][r][c][f] < t[0][r][c][f]) ? 1 : 0;
                 p->var[r][c][f] = v;
-                if (seen[r][c][f])
+                if (tuned)
                     out += "r" + std::to_string(r) + "c" + std::to_string(c) + "f" +
                            std::to_string(f) + "=" + std::to_string(v) + ";";
             }

@@ -159,6 +159,66 @@ def batch_systems(shapes, seed: int, **kw):
     return [random_hpd(N, m, k, seed * 1000 + i, **kw) for i, (N, m, k) in enumerate(shapes)]
 
 
+_PACK = {}
+
+
+def _pack_one(i):
+    from multiprocessing import shared_memory
+    from threadpoolctl import threadpool_limits
+    st = _PACK
+    N, m, k = st["shapes"][i]
+    with threadpool_limits(1):  # one BLAS thread per worker process
+        q = random_hpd(N, m, k, st["seed"] * 1000 + i)
+    for name, arr, off in (("A", q.A, st["offA"][i]), ("B", q.B, st["offB"][i]),
+                           ("y", q.y, st["offy"][i])):
+        shm = shared_memory.SharedMemory(name=st["shm"][name])
+        dst = np.ndarray((st["tot"][name],), dtype=np.complex128, buffer=shm.buf)
+        dst[off:off + arr.size] = arr.ravel()
+        del dst
+        shm.close()
+    return i
+
+
+def batch_packed(shapes, seed: int, workers: int = 1):
+    """The systems of ``batch_systems(shapes, seed)`` packed back to back:
+    flat (A, B, y) arrays in the library's batch layout.  With ``workers`` > 1
+    the systems are drawn by forked worker processes into shared memory
+    (same values: every system has its own generator).  Fork only from a
+    process that has not initialised a GPU."""
+    offA, offB, offy = [0], [0], [0]
+    for N, m, k in shapes:
+        offA.append(offA[-1] + N * m * m)
+        offB.append(offB[-1] + (N - 1) * m * m)
+        offy.append(offy[-1] + N * m * k)
+    tot = {"A": offA[-1], "B": offB[-1], "y": offy[-1]}
+    if workers <= 1:
+        out = {n: np.empty(tot[n], np.complex128) for n in tot}
+        for i, (N, m, k) in enumerate(shapes):
+            q = random_hpd(N, m, k, seed * 1000 + i)
+            out["A"][offA[i]:offA[i + 1]] = q.A.ravel()
+            out["B"][offB[i]:offB[i + 1]] = q.B.ravel()
+            out["y"][offy[i]:offy[i + 1]] = q.y.ravel()
+        return out["A"], out["B"], out["y"]
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    shms = {n: shared_memory.SharedMemory(create=True, size=max(tot[n], 1) * 16) for n in tot}
+    try:
+        _PACK.clear()
+        _PACK.update(shapes=list(shapes), seed=seed, offA=offA, offB=offB, offy=offy, tot=tot,
+                     shm={n: shms[n].name for n in shms})
+        with mp.get_context("fork").Pool(workers) as pool:
+            for _ in pool.imap_unordered(_pack_one, range(len(shapes))):
+                pass
+        out = [np.ndarray((tot[n],), dtype=np.complex128, buffer=shms[n].buf).copy()
+               for n in ("A", "B", "y")]
+    finally:
+        for sh in shms.values():
+            sh.close()
+            sh.unlink()
+        _PACK.clear()
+    return tuple(out)
+
+
 # The named workloads (sizes as the paper's problem statement instantiates them)
 TINY = dict(N=64, m=4, k=1)                 # one system, plus an indefinite twin
 LARGE = dict(N=65536, m=32, k=16)           # large single system
