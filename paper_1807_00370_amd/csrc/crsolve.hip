@@ -439,7 +439,8 @@ void run_cvt(const Ctx& c, const CvtLaunch& L, const void* A, const void* B, con
 {
     const void* src = L.user_src ? (L.which == 0 ? A : (L.which == 1 ? B : y)) : c.ws;
     Timed tm(c.p, KID_CONVERT, c.st);
-    const unsigned g = (unsigned)std::min<int64_t>((L.total + 255) / 256, 1 << 16);
+    const int64_t per = 256 * crs::kCvtPer;
+    const unsigned g = (unsigned)std::min<int64_t>((L.total + per - 1) / per, 1 << 16);
     const CvtJob* jb = c.djobs + L.job0;
     if (L.f64_src && !L.f64_dst)
         hipLaunchKernelGGL((crs::k_convert<double, float>), dim3(g), dim3(256), 0, c.st, jb,
@@ -594,7 +595,11 @@ int build_plan(crsolve_plan* p)
     const bool io64 = refine || f64native;
     if (io64) {
         p->off_part = a.off;
-        a.off = align_up(a.off + sizeof(double) * 2 * (size_t)std::max<int64_t>(p->totN, 1));
+        // one pair of partial sums per (block row, 16-row tile)
+        int64_t nparts = 0;
+        for (int s = 0; s < p->batch; ++s)
+            nparts += (int64_t)p->N[s] * ((p->m[s] + 15) / 16);
+        a.off = align_up(a.off + sizeof(double) * 2 * (size_t)std::max<int64_t>(nparts, 1));
         p->off_norms = a.off;
         a.off = align_up(a.off + sizeof(double) * 2 * p->batch);
     }
@@ -754,9 +759,11 @@ int build_plan(crsolve_plan* p)
 
     // whole-system segments: gradients or residuals (one work item per block
     // row) and norms (one per system)
+    // first residual partial-sum pair of each system: one pair per (block
+    // row, 16-row tile)
     std::vector<int64_t> rowbase(p->batch, 0);
     for (int s = 1; s < p->batch; ++s)
-        rowbase[s] = rowbase[s - 1] + p->N[s - 1];
+        rowbase[s] = rowbase[s - 1] + (int64_t)p->N[s - 1] * ((p->m[s - 1] + 15) / 16);
     auto sys_seg = [&](int s) {
         Seg g;
         std::memset(&g, 0, sizeof(g));
@@ -789,7 +796,10 @@ int build_plan(crsolve_plan* p)
                     if (refine)
                         g.og = p->lv[s][0].oy; // r lands where level 0 reads its rhs
                     g.w0 = L.total;
-                    L.total += p->N[s];
+                    // gradients: one work item per block row; residuals: one
+                    // per (block row, 16-row tile)
+                    L.total += kind == 0 ? (int64_t)p->N[s]
+                                         : (int64_t)p->N[s] * ((p->m[s] + 15) / 16);
                     p->segs.push_back(g);
                     ++L.nseg;
                 }
@@ -981,20 +991,9 @@ void residual(const Ctx& c, const void* A, const void* B, const void* x, const v
     void* R = store_r ? (void*)c.ws : nullptr;
     for (const Launch& L : p->resid) {
         Timed tm(p, KID_RESIDUAL, c.st);
-#define CALL(MT)                                                                                   \
-    hipLaunchKernelGGL((crs::k_residual<MT>), dim3((unsigned)L.total), dim3(64), 0, c.st,          \
-                       c.dsegs + L.seg0, L.nseg, L.total, (const cx<double>*)A,                    \
-                       (const cx<double>*)B, (const cx<double>*)x, (const cx<double>*)y, R,        \
-                       L.f64 ? 0 : 1, part)
-        switch (L.cls) {
-        case 0: CALL(4); break;
-        case 1: CALL(8); break;
-        case 2: CALL(16); break;
-        case 3: CALL(32); break;
-        case 4: CALL(64); break;
-        default: CALL(256); break;
-        }
-#undef CALL
+        hipLaunchKernelGGL(crs::k_residual, dim3(grid8(L.total)), dim3(64), 0, c.st,
+                           c.dsegs + L.seg0, L.nseg, L.total, (const cx<double>*)A, (const cx<double>*)B,
+                           (const cx<double>*)x, (const cx<double>*)y, R, L.f64 ? 0 : 1, part);
     }
     Timed tm(p, KID_NORMS, c.st);
     hipLaunchKernelGGL(crs::k_norms, dim3(p->batch), dim3(256), 0, c.st, c.dsegs + p->norm_seg0,
@@ -1116,6 +1115,116 @@ void enqueue_refine_pass(const Ctx& c, const void* A, const void* B, const void*
     residual(c, A, B, x, y, true);
 }
 
+// The factorization fused with the first solve pass of the mixed form:
+// conversions, all levels down with matrix and right-hand side together, back
+// substitution, x = d, then the FP64 residual and its norms.
+void enqueue_refine_fused(const Ctx& c, const void* A, const void* B, const void* y, void* x)
+{
+    for (const CvtLaunch& cl : c.p->cvt_factor0)
+        run_cvt(c, cl, A, B, nullptr);
+    for (const CvtLaunch& cl : c.p->cvt_solve0)
+        run_cvt(c, cl, nullptr, nullptr, y);
+    init_flags(c);
+    levels_down(c, A, B, nullptr, 1, 1);
+    levels_up(c, x);
+    update(c, x, 1);
+    residual(c, A, B, x, y, true);
+}
+
+// Refinement after a first pass whose residual norms are in the workspace:
+// d = A^{-1} r with the mixed factors and x += d until every system meets
+// rtol (or max_refine passes); writes refine_iters and rel_residual.
+template <class Pass>
+int refine_iterate(const crsolve_plan* p, const Ctx& c, Pass pass, crsolve_info* info)
+{
+    std::vector<double> nh, tab(2 * p->batch, 0.0);
+    int it = 0, rc;
+    for (;;) {
+        if ((rc = read_norms(c, nh)))
+            return rc;
+        bool done = true;
+        for (int s = 0; s < p->batch; ++s) {
+            const double rel = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
+            tab[2 * s] = it;
+            tab[2 * s + 1] = rel;
+            if (!(rel <= p->rtol))
+                done = false;
+        }
+        if (done || it >= p->max_refine)
+            break;
+        if ((rc = pass(false)))
+            return rc;
+        ++it;
+    }
+    return write_refine_info(c, info, tab);
+}
+
+// FP64 fallback after a breakdown of the mixed factorization: factor and
+// solve with the FP64 plan, then the residual for the record.
+int fallback_fs(const crsolve_plan* p, const Ctx& c, const void* A, const void* B, const void* y,
+                void* x, crsolve_info* info)
+{
+    const crsolve_plan* q = p->fb.get();
+    Ctx cf = make_ctx(q, c.ws + p->off_fb, c.st);
+    int rc = upload(q, cf.ws, c.st);
+    if (rc)
+        return rc;
+    init_flags(cf);
+    levels_down(cf, A, B, y, 1, 1);
+    levels_up(cf, x);
+    finalize(cf, info, 1);
+    residual(c, A, B, x, y, false);
+    std::vector<double> nh, tab(2 * p->batch, 0.0);
+    if ((rc = read_norms(c, nh)))
+        return rc;
+    for (int s = 0; s < p->batch; ++s)
+        tab[2 * s + 1] = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
+    return write_refine_info(c, info, tab);
+}
+
+// crsolve_factor_solve of the mixed form: the fused first pass, one
+// synchronization for the breakdown flags and the residual norms, then either
+// the refinement passes or the FP64 fallback.
+int factor_solve_refine(const crsolve_plan* p, const void* A, const void* B, const void* y,
+                        void* x, char* ws, crsolve_info* info, hipStream_t st)
+{
+    Ctx c = make_ctx(p, ws, st);
+    int rc;
+    if (p->graphs_on) {
+        rc = with_graph(p, gkey(4, {A, B, y, x, ws}), ws, st,
+                        [&](const Ctx& g) { enqueue_refine_fused(g, A, B, y, x); });
+        if (rc)
+            return rc;
+    } else {
+        if ((rc = upload(p, ws, st)))
+            return rc;
+        enqueue_refine_fused(c, A, B, y, x);
+    }
+    std::vector<unsigned long long> fl(p->batch);
+    if (hipMemcpyAsync(fl.data(), c.flags, sizeof(unsigned long long) * p->batch,
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return CRSOLVE_EHIP;
+    bool failed = false;
+    for (unsigned long long f : fl)
+        failed |= f != crs::kNoFail;
+    p->use_fb = failed;
+    if (failed)
+        return fallback_fs(p, c, A, B, y, x, info);
+    finalize(c, info, 0);
+    auto pass = [&](bool first) -> int {
+        if (!p->graphs_on) {
+            enqueue_refine_pass(c, A, B, y, x, first);
+            return CRSOLVE_OK;
+        }
+        return with_graph(p, gkey(3, {A, B, y, x, ws}), ws, st,
+                          [&](const Ctx& g) { enqueue_refine_pass(g, A, B, y, x, first); });
+    };
+    if ((rc = refine_iterate(p, c, pass, info)))
+        return rc;
+    return last_err();
+}
+
 // FP32 factorization with FP64 tail; on breakdown, the FP64 plan takes over.
 int factor_refine(const crsolve_plan* p, const void* A, const void* B, char* ws,
                   crsolve_info* info, hipStream_t st)
@@ -1191,27 +1300,7 @@ int solve_refine(const crsolve_plan* p, char* ws, const void* A, const void* B, 
     // x_0 = A^{-1} y with the mixed factors, then its residual
     if ((rc = pass(true)))
         return rc;
-    int it = 0;
-    for (;;) {
-        if ((rc = read_norms(c, nh)))
-            return rc;
-        bool done = true;
-        for (int s = 0; s < p->batch; ++s) {
-            const double rel = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
-            tab[2 * s] = it;
-            tab[2 * s + 1] = rel;
-            if (!(rel <= p->rtol))
-                done = false;
-        }
-        if (done || it >= p->max_refine)
-            break;
-        // d = A^{-1} r with the mixed factors (r was written where level 0
-        // reads its right-hand side), x += d, new residual
-        if ((rc = pass(false)))
-            return rc;
-        ++it;
-    }
-    if ((rc = write_refine_info(c, info, tab)))
+    if ((rc = refine_iterate(p, c, pass, info)))
         return rc;
     return last_err();
 }
@@ -1568,11 +1657,8 @@ int crsolve_factor_solve(crsolve_plan* p, const void* A, const void* B, const vo
     const size_t es = io_esz(p);
     if (!aligned(A, es) || (any_B(p) && !aligned(B, es)) || !aligned(y, es) || !aligned(x, es))
         return CRSOLVE_EINVAL;
-    if (p->prec == CRSOLVE_PREC_FP32_REFINE) {
-        if ((rc = factor_refine(p, A, B, (char*)ws, info, (hipStream_t)stream)))
-            return rc;
-        return solve_refine(p, (char*)ws, A, B, y, x, info, (hipStream_t)stream);
-    }
+    if (p->prec == CRSOLVE_PREC_FP32_REFINE)
+        return factor_solve_refine(p, A, B, y, x, (char*)ws, info, (hipStream_t)stream);
     if (p->graphs_on) {
         rc = with_graph(p, gkey(0, {A, B, y, x, ws, info}), (char*)ws, (hipStream_t)stream,
                         [&](const Ctx& g) { enqueue_native_fs(g, A, B, y, x, info); });

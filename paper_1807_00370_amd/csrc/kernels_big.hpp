@@ -124,6 +124,61 @@ __device__ __forceinline__ void wave_mm(typename MF<T>::v4 (&cr)[RM][RN],
     }
 }
 
+// (cr, ci) += H Y for the 16 x 16 tile with rows row0.. of H and columns of
+// the right operand Y, where H is the Hermitian matrix read from the lower
+// triangle and the real diagonal of the m x m row-major block A:
+// H[i][t] = A[i][t] (t < i), Re A[i][i] (t = i), conj(A[t][i]) (t > i);
+// contraction over all m columns, loaded as in wave_mm.
+template <class T, int G>
+__device__ __forceinline__ void wave_mm_herm(typename MF<T>::v4& cr, typename MF<T>::v4& ci,
+                                             const cx<T>* __restrict__ A, int m, int row0,
+                                             const WOp<T> B)
+{
+    const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+    const int kd = m, ng = (kd + 4 * G - 1) / (4 * G);
+    const int i = row0 + cc;
+    const bool oa = i < m, ob = cc < B.no;
+    const cx<T>* pb = B.p + ((ob ? cc : 0) * B.so + kr * B.st);
+    const int sb = 4 * B.st;
+    cx<T> xa0[G], yb0[G], xa1[G], yb1[G];
+    auto load = [&](cx<T>(&xa)[G], cx<T>(&yb)[G], int g) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int ks = g * G + u, t = 4 * ks + kr;
+            const bool ok = t < kd;
+            cx<T> a = czero<T>();
+            if (ok && oa) {
+                a = A[t <= i ? i * m + t : t * m + i];
+                a.i = t < i ? a.i : (t == i ? T(0) : -a.i);
+            }
+            xa[u] = a;
+            yb[u] = (ok && ob) ? pb[ks * sb] : czero<T>();
+        }
+    };
+    auto comp = [&](const cx<T>(&xa)[G], const cx<T>(&yb)[G]) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            cr = MF<T>::mma(xa[u].r, yb[u].r, cr);
+            cr = MF<T>::mma(-xa[u].i, yb[u].i, cr);
+            ci = MF<T>::mma(xa[u].r, yb[u].i, ci);
+            ci = MF<T>::mma(xa[u].i, yb[u].r, ci);
+        }
+    };
+    load(xa0, yb0, 0);
+    for (int g = 0; g < ng; g += 2) {
+        if (g + 1 < ng)
+            load(xa1, yb1, g + 1);
+        comp(xa0, yb0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (g + 1 < ng) {
+            if (g + 2 < ng)
+                load(xa0, yb0, g + 2);
+            comp(xa1, yb1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 template <class T, int RM, int RN>
 __device__ __forceinline__ void zero_acc(typename MF<T>::v4 (&cr)[RM][RN],
                                          typename MF<T>::v4 (&ci)[RM][RN])
