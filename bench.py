@@ -228,10 +228,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(form, kernel):
+def measured_traffic(form, kernel, shape=(65536, 32, 16)):
     """HBM bytes per launch from the committed counter summary of this
     workload, or None when the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s_N65536_m32_k16.json" % form)
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s_N%d_m%d_k%d.json" % ((form,) + shape))
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -243,7 +243,7 @@ def measured_traffic(form, kernel):
     return None if k is None else k["traffic_bytes_per_launch"]
 
 
-def roofline(per_step, mod, prec_f64, form="fp64"):
+def roofline(per_step, mod, prec_f64, form="fp64", shape=(65536, 32, 16)):
     timed = [kn for kn in mod if kn in per_step]
     dom = max(timed, key=lambda kn: per_step[kn][1])
     launches, kms = per_step[dom]
@@ -257,7 +257,7 @@ def roofline(per_step, mod, prec_f64, form="fp64"):
         ach = flops / launches / (avg_ms * 1e-3) / 1e12
         r = {"bound": "mfma", "achieved": ach, "peak": peak_f, "unit": "TFLOP/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = measured_traffic(form, dom)
+    r["traffic"] = measured_traffic(form, dom, shape)
     r["kernel"] = dom
     r["avg_launch_ms"] = avg_ms
     r["launches_per_step"] = launches
@@ -455,6 +455,8 @@ def main():
                          "Poisson system N=4096, m=256, k=1 with an eigenvector right-hand side")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel variants (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="one plain device copy of A (known size) before timing, to calibrate "
                          "HBM byte counters")
@@ -508,7 +510,8 @@ def main():
         else:
             sol = Solver([s.N], [s.m], [s.k], dtype=torch.complex128, precision="fp32_refine",
                          device=dev, rtol=rtol, max_refine=30, fp64_tail_blocks=TAIL)
-        tuning = sol.autotune(A, B, y) if form == "fp64" and s.m <= 64 and not pcr else None
+        tuning = (sol.autotune(A, B, y) if form == "fp64" and s.m <= 64 and not pcr
+                  and not args.no_autotune else None)
         ms, ms_eager, per_step = time_form(torch, sol, A, B, y, x, args.steps, args.warmup)
         info = sol.info_host()[0]
         if info["status"] != 0:
@@ -527,7 +530,8 @@ def main():
             "fp64_fallback": int(info["fp64_fallback"]) if form != "fp64" else 0,
             "kernel_ms_per_step": {kn: round(v[1], 4) for kn, v in per_step.items()},
             "kernel_launches_per_step": {kn: v[0] for kn, v in per_step.items()},
-            "roofline": roofline(per_step, mod, form == "fp64", ("pcr_" if pcr else "") + form),
+            "roofline": roofline(per_step, mod, form == "fp64", ("pcr_" if pcr else "") + form,
+                                 (s.N, s.m, s.k)),
             "model_bytes": sum(v[0] for v in mod.values()),
             "model_flops": sum(v[1] for v in mod.values()),
         }
