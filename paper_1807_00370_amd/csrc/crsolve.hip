@@ -278,7 +278,7 @@ struct Disp {
                      const unsigned long long* flags, hipStream_t st, int variant)
     {
         if ((MT == 16 || MT == 32) && variant == 0) {
-            hipLaunchKernelGGL((crs::k_back_m<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
+            hipLaunchKernelGGL((crs::k_back_mf<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
         } else {
             constexpr int PW = 32;

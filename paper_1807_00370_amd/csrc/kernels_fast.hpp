@@ -342,6 +342,41 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
     }
 }
 
+// Replaces the packed lower triangle L (m <= 16 S, diagonal {L_cc, 1/L_cc})
+// held in LDS by the inverses D_I = L_II^{-1} of its 16 x 16 diagonal tiles,
+// sL[I * 256 + q * 16 + j] = D_I[q][j]: lane j < 16 S forms column j & 15 of
+// D_{j / 16} by forward substitution (padded rows are identity rows).  Every
+// lane of the work-group must call it.
+template <class T, int S>
+__device__ __forceinline__ void inverse_tiles_lds(cx<T>* sL, int m)
+{
+    const int lane = threadIdx.x & 63;
+    const int I0 = (lane >> 4) < S ? (lane >> 4) : 0, jj = lane & 15;
+    cx<T> z[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int gq = 16 * I0 + q;
+        cx<T> v = q == jj ? cx<T>{T(1), T(0)} : czero<T>();
+        if (gq < m) {
+            const int base = gq * (gq + 1) / 2 + 16 * I0;
+#pragma unroll
+            for (int u = 0; u < q; ++u)
+                msub(v, sL[base + u], z[u]);
+            const T iq = sL[base + q].i;
+            v = cx<T>{v.r * iq, v.i * iq};
+        }
+        z[q] = v;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads(); // every read of L in LDS is done
+    if (lane < 16 * S) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            sL[I0 * 256 + q * 16 + jj] = z[q];
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- k_elim_mf
 
 // Elimination for block sizes 8 < m <= 32 with the forward substitutions on
@@ -472,38 +507,14 @@ __global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs,
     }
     __syncthreads();
 
-    // left operands: L_10 and the D tiles (lane j < 16 S forms column j & 15
-    // of D_{j / 16} by forward substitution; padded rows are identity rows)
+    // left operands: L_10, then the D tiles
     cx<T> aL[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = 16 + cc, u = MF<T>::row(kr, v);
         aL[v] = (S == 2 && i < m) ? sL[i * (i + 1) / 2 + u] : czero<T>();
     }
-    const int I0 = (lane >> 4) < S ? (lane >> 4) : 0, jj = lane & 15;
-    cx<T> z[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int gq = 16 * I0 + q;
-        cx<T> v = q == jj ? cx<T>{T(1), T(0)} : czero<T>();
-        if (gq < m) {
-            const int base = gq * (gq + 1) / 2 + 16 * I0;
-#pragma unroll
-            for (int u = 0; u < q; ++u)
-                msub(v, sL[base + u], z[u]);
-            const T iq = sL[base + q].i;
-            v = cx<T>{v.r * iq, v.i * iq};
-        }
-        z[q] = v;
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    __syncthreads(); // every read of L in LDS is done
-    if (lane < 16 * S) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            sL[I0 * 256 + q * 16 + jj] = z[q];
-    }
-    __syncthreads();
+    inverse_tiles_lds<T, S>(sL, m);
     cx<T> aD[S][4];
 #pragma unroll
     for (int I = 0; I < S; ++I)
@@ -978,6 +989,136 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_back_m(const Seg* 
                 for (int r = 0; r < MT; ++r)
                     if (r < m)
                         xp[r * k + c0 + lane] = x[r];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- k_back_mf
+
+// Back substitution for block sizes 8 < m <= 32 on MFMA: per 16-column strip
+// of x_p, w = g - Q x_{p-d} - P x_{p+d} stays in the accumulators and the
+// block upper triangular L^H x = w is solved tile by tile,
+// x_1 = D_1^H w_1, x_0 = D_0^H (w_0 - L_10^H x_1), with the products chained
+// through the accumulators as in k_elim_mf (D_I = L_II^{-1} formed from L).
+template <class T, int MT>
+__global__ __launch_bounds__(64, 2) void k_back_mf(const Seg* __restrict__ segs, int nseg,
+                                                   int64_t total, const cx<T>* __restrict__ W,
+                                                   cx<T>* __restrict__ X,
+                                                   const unsigned long long* __restrict__ flags)
+{
+    static_assert(MT == 16 || MT == 32, "one or two 16-row tiles");
+    using v4 = typename MF<T>::v4;
+    constexpr int S = MT / 16, KS = MT / 4;
+    constexpr int NP = MT * (MT + 1) / 2;
+    constexpr int NS = NP > S * 256 ? NP : S * 256;
+    __shared__ cx<T> sL[NS]; // packed L, later the D tiles
+    const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
+    const int64_t w = blockIdx.x;
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int p = s.e0 + (int)t * s.es;
+    const int m = s.m, k = s.k, d = s.d;
+    const bool hasPrev = p - d >= 0, hasNext = p + d < s.n;
+    const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
+    cx<T>* xp = X + s.ox + (s.xo + s.xs * p) * mk;
+    if (flags[s.sys] != kNoFail) {
+        const T nan = T(NAN);
+        for (int e = lane; e < m * k; e += 64)
+            xp[e] = cx<T>{nan, nan};
+        return;
+    }
+    const cx<T>* xm = X + s.ox + (s.xo + s.xs * (p - d)) * mk;
+    const cx<T>* xn = X + s.ox + (s.xo + s.xs * (p + d)) * mk;
+    const cx<T>* L = W + s.oL + t * mm;
+    const cx<T>* P = W + s.oP + t * mm;
+    const cx<T>* Q = W + s.oQ + t * mm;
+    const cx<T>* g = W + s.og + t * mk;
+    for (int e = lane; e < m * (m + 1) / 2; e += 64)
+        sL[e] = L[e];
+    __syncthreads();
+    // left operands: (L_10^H)[i][u] = conj(L[16 + u][i]), then (D_I^H)[i][u] =
+    // conj(D_I[u][i])
+    cx<T> aLh[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int u = 16 + MF<T>::row(kr, v);
+        const cx<T> a = (S == 2 && u < m) ? sL[u * (u + 1) / 2 + cc] : czero<T>();
+        aLh[v] = cx<T>{a.r, -a.i};
+    }
+    inverse_tiles_lds<T, S>(sL, m);
+    cx<T> aDh[S][4];
+#pragma unroll
+    for (int I = 0; I < S; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const cx<T> a = sL[I * 256 + MF<T>::row(kr, v) * 16 + cc];
+            aDh[I][v] = cx<T>{a.r, -a.i};
+        }
+#pragma unroll 1
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        const int cw = min(16, k - c0);
+        // w_I = g_I - Q_I x_{p-d} - P_I x_{p+d} in the accumulator layout
+        T wr[S][4], wi[S][4];
+#pragma unroll
+        for (int I = 0; I < S; ++I) {
+            v4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+            if (hasPrev)
+                tile_nn<T, KS>(cr, ci, Q, m, m, 16 * I, xm + c0, k, cw, 0, m);
+            if (hasNext)
+                tile_nn<T, KS>(cr, ci, P, m, m, 16 * I, xn + c0, k, cw, 0, m);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * I + MF<T>::row(kr, v);
+                const cx<T> gv = (r < m && cc < cw) ? g[r * k + c0 + cc] : czero<T>();
+                wr[I][v] = gv.r - cr[v];
+                wi[I][v] = gv.i - ci[v];
+            }
+        }
+        // bottom tile first: x_{S-1} = D_{S-1}^H w_{S-1}
+        v4 x1r = {0, 0, 0, 0}, x1i = {0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const cx<T> a = aDh[S - 1][v];
+            x1r = MF<T>::mma(a.r, wr[S - 1][v], x1r);
+            x1r = MF<T>::mma(-a.i, wi[S - 1][v], x1r);
+            x1i = MF<T>::mma(a.r, wi[S - 1][v], x1i);
+            x1i = MF<T>::mma(a.i, wr[S - 1][v], x1i);
+        }
+        v4 x0r = x1r, x0i = x1i;
+        if (S == 2) {
+            // w_0 -= L_10^H x_1, x_0 = D_0^H w_0
+            v4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const cx<T> a = aLh[v];
+                tr = MF<T>::mma(a.r, x1r[v], tr);
+                tr = MF<T>::mma(-a.i, x1i[v], tr);
+                ti = MF<T>::mma(a.r, x1i[v], ti);
+                ti = MF<T>::mma(a.i, x1r[v], ti);
+            }
+            x0r = v4{0, 0, 0, 0};
+            x0i = v4{0, 0, 0, 0};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const cx<T> a = aDh[0][v];
+                const T br = wr[0][v] - tr[v], bi = wi[0][v] - ti[v];
+                x0r = MF<T>::mma(a.r, br, x0r);
+                x0r = MF<T>::mma(-a.i, bi, x0r);
+                x0i = MF<T>::mma(a.r, bi, x0i);
+                x0i = MF<T>::mma(a.i, br, x0i);
+            }
+        }
+        if (cc < cw) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r0 = MF<T>::row(kr, v);
+                if (r0 < m)
+                    xp[r0 * k + c0 + cc] = cx<T>{x0r[v], x0i[v]};
+                if (S == 2 && 16 + r0 < m)
+                    xp[(16 + r0) * k + c0 + cc] = cx<T>{x1r[v], x1i[v]};
             }
         }
     }
