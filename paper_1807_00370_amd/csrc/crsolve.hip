@@ -408,7 +408,7 @@ void run_back(const Ctx& c, const Launch& L, void* x)
     Timed tm(c.p, KID_BACK, c.st, L.cls, L.f64);
     if (tiled(L.cls)) {
         const BigDims b = big_dims(c.p, L);
-        hipLaunchKernelGGL((crs::k_back_big<T>), dim3(grid8(L.total * b.K16)), dim3(64), 0, c.st,
+        hipLaunchKernelGGL((crs::k_back_big<T>), dim3(grid8(L.total * b.K16)), dim3(64 * b.S), 0, c.st,
                            c.dsegs + L.seg0, L.nseg, L.total, b.K16, (const cx<T>*)c.ws, (cx<T>*)X,
                            c.flags);
         return;

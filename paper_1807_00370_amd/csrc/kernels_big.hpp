@@ -16,8 +16,8 @@
 //   k_reduce_big  one wave per (kept block, 32 x 32 tile) of the reduced
 //                 system A' = A_q - P_l^H P_l - Q_r^H Q_r (lower triangle),
 //                 B' = -P_r^H Q_r, y' = y_q - P_l^H g_l - Q_r^H g_r.
-//   k_back_big    one wave per (eliminated block, 16-column strip of x_p):
-//                 blocked back substitution of
+//   k_back_big    one work-group per (eliminated block, 16-column strip of
+//                 x_p), one wave per row tile: blocked back substitution of
 //                 L^H x_p = g_p - Q_p x_{p-d} - P_p x_{p+d}.
 //   k_grad_big    one wave per (block row, 32 x 32 tile) of the adjoint's
 //                 gradient blocks.
@@ -564,15 +564,26 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
 
 // -------------------------------------------------------------- k_back_big
 
+// One work-group per (eliminated block, 16-column strip of x_p), one wave per
+// 16-row tile J of the block (blockDim = 64 x the largest tile count of the
+// launch; waves beyond a block's S tiles only join the barriers):
+//   phase A, all waves at once: w_J = g_J - Q_J x_{p-d} - P_J x_{p+d}, kept
+//     in the MFMA accumulators;
+//   phase B, bottom-up over the tiles I: wave I forms x_I = D_I^H w_I (the
+//     accumulator is the right operand, see k_trsm_big), stores it and
+//     publishes it in LDS; every wave J < I then applies
+//     w_J -= L_IJ^H x_I (its operand loaded one step ahead).
+// The block's serial chain is S short steps instead of S full tile sweeps.
 template <class T>
-__global__ __launch_bounds__(64) void k_back_big(const Seg* __restrict__ segs, int nseg,
-                                                 int64_t total, int nstrip,
-                                                 const cx<T>* __restrict__ W,
-                                                 cx<T>* __restrict__ X,
-                                                 const unsigned long long* __restrict__ flags)
+__global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs, int nseg,
+                                                   int64_t total, int nstrip,
+                                                   const cx<T>* __restrict__ W,
+                                                   cx<T>* __restrict__ X,
+                                                   const unsigned long long* __restrict__ flags)
 {
     using v4 = typename MF<T>::v4;
-    const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
+    __shared__ cx<T> sx[256]; // x_I, row-major 16 x 16
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
     const int64_t li = xcd_item();
     const int64_t w = li / nstrip;
     const int u = (int)(li - w * nstrip);
@@ -591,7 +602,7 @@ __global__ __launch_bounds__(64) void k_back_big(const Seg* __restrict__ segs, i
     cx<T>* xp = X + s.ox + (s.xo + s.xs * p) * mk;
     if (flags[s.sys] != kNoFail) {
         const T nan = T(NAN);
-        for (int e = lane; e < m * 16; e += 64)
+        for (int e = threadIdx.x; e < m * 16; e += blockDim.x)
             if ((e & 15) < nc)
                 xp[(e >> 4) * k + c0 + (e & 15)] = cx<T>{nan, nan};
         return;
@@ -603,41 +614,81 @@ __global__ __launch_bounds__(64) void k_back_big(const Seg* __restrict__ segs, i
     const cx<T>* Q = W + s.oQ + t * mm;
     const cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
     const cx<T>* g = W + s.og + t * mk;
+    const bool own = wv < S;
+    const int r0 = 16 * wv;
+    // D_J^H operand of this wave's own tile: (D^H)[cc][rr] = conj(D[rr][cc])
+    cx<T> aD[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        aD[v] = own ? Dg[wv * 256 + MF<T>::row(kr, v) * 16 + cc] : czero<T>();
+    // phase A
+    v4 cr[1][1], ci[1][1];
+    zero_acc<T, 1, 1>(cr, ci);
+    if (own && hasPrev)
+        wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{Q + (int64_t)r0 * m, m, 1, m - r0},
+                                          WOp<T>{xm + c0, 1, k, nc}, m);
+    if (own && hasNext)
+        wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{P + (int64_t)r0 * m, m, 1, m - r0},
+                                          WOp<T>{xn + c0, 1, k, nc}, m);
+    v4 wr, wi;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = r0 + MF<T>::row(kr, v);
+        const cx<T> gv = (own && r < m && cc < nc) ? g[r * k + c0 + cc] : czero<T>();
+        wr[v] = gv.r - cr[0][0][v];
+        wi[v] = gv.i - ci[0][0][v];
+    }
+    // operand of the update at step I: A(i, t) = conj(L[16 I + t][r0 + i]),
+    // lane (cc, kr) holds t = 4 s + kr for the contraction steps s
+    auto load_l = [&](int I, cx<T>(&a)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = 16 * I + 4 * q + kr;
+            a[q] = (own && wv < I && row < m) ? L[(int64_t)row * m + r0 + cc] : czero<T>();
+        }
+    };
+    cx<T> an[4];
+    load_l(S - 1, an);
+    // phase B
     for (int I = S - 1; I >= 0; --I) {
-        const int r0 = 16 * I;
-        v4 cr[1][1], ci[1][1];
-        zero_acc<T, 1, 1>(cr, ci);
-        if (hasPrev)
-            wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{Q + (int64_t)r0 * m, m, 1, m - r0},
-                                              WOp<T>{xm + c0, 1, k, nc}, m);
-        if (hasNext)
-            wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{P + (int64_t)r0 * m, m, 1, m - r0},
-                                              WOp<T>{xn + c0, 1, k, nc}, m);
-        // sum over the tiles below of L[J][I]^H x_J
-        wave_mm<T, 1, 1, true, false, 4>(cr, ci, WOp<T>{L + (int64_t)(r0 + 16) * m + r0, 1, m, m - r0},
-                                         WOp<T>{xp + (int64_t)(r0 + 16) * k + c0, 1, k, nc},
-                                         m - r0 - 16);
-        // x_I = D_I^H (g_I - acc), with the accumulator as the right operand
-        // (see k_trsm_big); (D^H)[cc][rr] = conj(D[rr][cc])
-        v4 xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+        cx<T> a[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int rr = MF<T>::row(kr, v), r = r0 + rr;
-            const cx<T> gg = (r < m && cc < nc) ? g[r * k + c0 + cc] : czero<T>();
-            const T br = gg.r - cr[0][0][v], bi = gg.i - ci[0][0][v];
-            const cx<T> a = Dg[I * 256 + rr * 16 + cc];
-            xr = MF<T>::mma(a.r, br, xr);
-            xr = MF<T>::mma(a.i, bi, xr);
-            xi = MF<T>::mma(a.r, bi, xi);
-            xi = MF<T>::mma(-a.i, br, xi);
-        }
+        for (int q = 0; q < 4; ++q)
+            a[q] = an[q];
+        if (I > 0)
+            load_l(I - 1, an);
+        if (wv == I) {
+            v4 xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + MF<T>::row(kr, v);
-            if (r < m && cc < nc)
-                xp[(int64_t)r * k + c0 + cc] = cx<T>{xr[v], xi[v]};
+            for (int v = 0; v < 4; ++v) {
+                const cx<T> q = aD[v];
+                xr = MF<T>::mma(q.r, wr[v], xr);
+                xr = MF<T>::mma(q.i, wi[v], xr);
+                xi = MF<T>::mma(q.r, wi[v], xi);
+                xi = MF<T>::mma(-q.i, wr[v], xi);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = MF<T>::row(kr, v), r = r0 + rr;
+                sx[rr * 16 + cc] = cx<T>{xr[v], xi[v]};
+                if (r < m && cc < nc)
+                    xp[(int64_t)r * k + c0 + cc] = cx<T>{xr[v], xi[v]};
+            }
         }
-        __syncthreads(); // the rows just stored are the next tiles' operands
+        __syncthreads();
+        if (wv < I) {
+            // w_J -= conj(L_IJ)^T x_I: contraction step q pairs t = 4 q + kr
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const cx<T> b = sx[(4 * q + kr) * 16 + cc];
+                const T ar = a[q].r, ai = -a[q].i; // conj(L)
+                wr = MF<T>::mma(-ar, b.r, wr);
+                wr = MF<T>::mma(ai, b.i, wr);
+                wi = MF<T>::mma(-ar, b.i, wi);
+                wi = MF<T>::mma(-ai, b.r, wi);
+            }
+        }
+        __syncthreads();
     }
 }
 
