@@ -346,6 +346,11 @@ BigDims big_dims(const crsolve_plan* p, const Launch& L)
     return b;
 }
 
+// FP64 tiled forward substitutions of launches with at least this many blocks
+// run one wave per strip (k_trsm_strip); fewer blocks, or FP32, take the
+// work-group form with its shorter chain and shared L tiles.
+constexpr int64_t kTrsmStripBlocks = 256;
+
 // Grid of the tiled kernels: a multiple of 8 work-groups (see xcd_item).
 unsigned grid8(int64_t items) { return (unsigned)((items + 7) / 8 * 8); }
 
@@ -366,10 +371,17 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
         }
         const int ns = (mat ? 2 * b.S : 0) + (rhs ? b.K16 : 0);
         if (ns > 0) {
+            constexpr int NC = crs::trsm_strips<T>();
+            const int ngrp = (ns + NC - 1) / NC;
             Timed tm(c.p, KID_TRSM, c.st, L.cls, L.f64);
-            hipLaunchKernelGGL((crs::k_trsm_big<T>), dim3(grid8(L.total * ns)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, ns, mat, rhs, (const cx<T>*)inB,
-                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+            if (sizeof(T) == 8 && L.total >= kTrsmStripBlocks)
+                hipLaunchKernelGGL((crs::k_trsm_strip<T>), dim3(grid8(L.total * ns)), dim3(64), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, ns, mat, rhs,
+                                   (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+            else
+                hipLaunchKernelGGL((crs::k_trsm_big<T>), dim3(grid8(L.total * ngrp)), dim3(64 * b.S),
+                                   0, c.st, c.dsegs + L.seg0, L.nseg, L.total, ngrp, mat, rhs,
+                                   (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
         }
         return;
     }

@@ -9,8 +9,9 @@
 //                 diagonal tile is factored in registers (one row per lane)
 //                 and its inverse D_I = L_II^{-1} is kept for the
 //                 substitutions; the tiles below become S_R D_I^H.
-//   k_trsm_big    one wave per (eliminated block, 16-column strip of
-//                 [B_p^H | B_{p-d} | y_p]): blocked forward substitution
+//   k_trsm_big    one work-group per (eliminated block, group of 16-column
+//                 strips of [B_p^H | B_{p-d} | y_p]), one wave per row tile:
+//                 blocked forward substitution
 //                 X_I = D_I (G_I - L[I][<I] X_{<I}), the Section 4 recipe
 //                 L \ G for the three operands of Eq. (Formulas).
 //   k_reduce_big  one wave per (kept block, 32 x 32 tile) of the reduced
@@ -337,10 +338,184 @@ __global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs,
 
 // -------------------------------------------------------------- k_trsm_big
 
-// Strips of a block: with_mat gives 2 S strips (columns of B_p^H, then of
-// B_{p-d}), with_rhs ceil(k / 16) strips of y_p after them.
+// Strips per work-group of the tiled forward substitution: every L tile a
+// wave loads serves this many 16-column strips.
 template <class T>
-__global__ __launch_bounds__(64) void k_trsm_big(const Seg* __restrict__ segs, int nseg,
+constexpr int trsm_strips()
+{
+    return sizeof(T) == 8 ? 2 : 4;
+}
+
+// One work-group per (eliminated block, group of NC = trsm_strips<T>()
+// 16-column strips of [B_p^H | B_{p-d} | y_p]), one wave per 16-row tile I
+// (blockDim = 64 x the largest tile count of the launch).  Strip u of a block
+// is a column strip of B_p^H for u < S, of B_{p-d} for u < 2 S (with_mat), of
+// y_p after them (with_rhs).  Top-down over the tiles J: wave J forms
+// X_J = D_J (G_J - acc_J), the accumulator being the right operand (see the
+// note in k_elim_mf), stores it and publishes it in LDS; every wave I > J
+// then accumulates acc_I += L_IJ X_J (its operand loaded one step ahead).
+template <class T>
+__global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs, int nseg,
+                                                   int64_t total, int ngrp, int with_mat,
+                                                   int with_rhs, const cx<T>* __restrict__ inB,
+                                                   const cx<T>* __restrict__ iny,
+                                                   cx<T>* __restrict__ W,
+                                                   const unsigned long long* __restrict__ flags)
+{
+    using v4 = typename MF<T>::v4;
+    constexpr int NC = trsm_strips<T>();
+    __shared__ cx<T> sx[NC][256]; // X_J of each strip, row-major 16 x 16
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+    const int64_t li = xcd_item();
+    const int64_t w = li / ngrp;
+    const int grp = (int)(li - w * ngrp);
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int p = s.e0 + (int)t * s.es;
+    const int m = s.m, k = s.k, d = s.d, S = (m + 15) >> 4;
+    if ((flags[s.sys] >> 40) < (unsigned long long)s.level)
+        return;
+    const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
+    const bool hasPrev = p - d >= 0, hasNext = p + d < s.n;
+    const int nmat = with_mat ? 2 * S : 0;
+    const int nstrip = nmat + (with_rhs ? (k + 15) / 16 : 0);
+    // per strip slot b: element (r, c) of the right-hand side is
+    // G[b][r * gr[b] + c * gc[b]] (conjugated for B_p^H), the solution goes
+    // to out[b][r * ld[b] + c], columns c0[b] .. c0[b] + nc[b] - 1
+    const cx<T>* G[NC];
+    cx<T>* out[NC];
+    int gr[NC], gc[NC], ld[NC], c0[NC], nc[NC];
+    bool cj[NC], on[NC];
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < NC; ++b) {
+        const int u = grp * NC + b;
+        int src = 2, cu = u - nmat;
+        if (u < nmat) {
+            src = u < S ? 0 : 1;
+            cu = u < S ? u : u - S;
+        }
+        on[b] = u < nstrip && (src == 0 ? hasNext : (src == 1 ? hasPrev : true));
+        c0[b] = 16 * cu;
+        const int ncol = src == 2 ? k : m;
+        nc[b] = on[b] ? min(16, ncol - c0[b]) : 0;
+        on[b] = on[b] && nc[b] > 0;
+        cj[b] = src == 0;
+        if (src == 0) {
+            G[b] = inB + s.oB + (int64_t)p * mm;
+            gr[b] = 1;
+            gc[b] = m;
+            out[b] = W + s.oP + t * mm;
+            ld[b] = m;
+        } else if (src == 1) {
+            G[b] = inB + s.oB + (int64_t)(p - d) * mm;
+            gr[b] = m;
+            gc[b] = 1;
+            out[b] = W + s.oQ + t * mm;
+            ld[b] = m;
+        } else {
+            G[b] = iny + s.oy + (int64_t)p * mk;
+            gr[b] = k;
+            gc[b] = 1;
+            out[b] = W + s.og + t * mk;
+            ld[b] = k;
+        }
+        any |= on[b];
+    }
+    if (!any)
+        return;
+    const cx<T>* Lg = W + s.oL + t * mm;
+    const cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
+    const bool own = wv < S;
+    const int r0 = 16 * wv;
+    // D_I operand of this wave's tile and its right-hand sides (accumulator layout)
+    cx<T> aD[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        aD[v] = own ? Dg[wv * 256 + cc * 16 + MF<T>::row(kr, v)] : czero<T>();
+    v4 ar[NC], ai[NC];
+#pragma unroll
+    for (int b = 0; b < NC; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + MF<T>::row(kr, v);
+            cx<T> x = czero<T>();
+            if (own && on[b] && r < m && cc < nc[b])
+                x = G[b][r * gr[b] + (c0[b] + cc) * gc[b]];
+            ar[b][v] = x.r;
+            ai[b][v] = cj[b] ? -x.i : x.i;
+        }
+    // operand of the update at step J: A(i, t) = L[r0 + i][16 J + t]
+    auto load_l = [&](int J, cx<T>(&a)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = (own && wv > J && r0 + cc < m) ? Lg[(int64_t)(r0 + cc) * m + 16 * J + 4 * q + kr]
+                                                  : czero<T>();
+        }
+    };
+    cx<T> an[4];
+    load_l(0, an);
+    for (int J = 0; J < S; ++J) {
+        cx<T> a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            a[q] = an[q];
+        if (J + 1 < S)
+            load_l(J + 1, an);
+        if (wv == J) {
+#pragma unroll
+            for (int b = 0; b < NC; ++b) {
+                if (!on[b])
+                    continue;
+                // X_J = D_J acc (acc holds G_J - sum of the updates)
+                v4 xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const cx<T> q = aD[v];
+                    xr = MF<T>::mma(q.r, ar[b][v], xr);
+                    xr = MF<T>::mma(-q.i, ai[b][v], xr);
+                    xi = MF<T>::mma(q.r, ai[b][v], xi);
+                    xi = MF<T>::mma(q.i, ar[b][v], xi);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = MF<T>::row(kr, v), r = r0 + rr;
+                    sx[b][rr * 16 + cc] = cx<T>{xr[v], xi[v]};
+                    if (r < m && cc < nc[b])
+                        out[b][(int64_t)r * ld[b] + c0[b] + cc] = cx<T>{xr[v], xi[v]};
+                }
+            }
+        }
+        __syncthreads();
+        if (own && wv > J) {
+#pragma unroll
+            for (int b = 0; b < NC; ++b) {
+                if (!on[b])
+                    continue;
+                // acc_I -= L_IJ X_J: contraction step q pairs t = 4 q + kr
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const cx<T> x = sx[b][(4 * q + kr) * 16 + cc];
+                    ar[b] = MF<T>::mma(-a[q].r, x.r, ar[b]);
+                    ar[b] = MF<T>::mma(a[q].i, x.i, ar[b]);
+                    ai[b] = MF<T>::mma(-a[q].r, x.i, ai[b]);
+                    ai[b] = MF<T>::mma(-a[q].i, x.r, ai[b]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One wave per (eliminated block, 16-column strip): the same substitution
+// with each wave sweeping all row tiles of its strip (no barriers).  Strips of
+// a block: with_mat gives 2 S strips (columns of B_p^H, then of B_{p-d}),
+// with_rhs ceil(k / 16) strips of y_p after them.  Used for FP64 levels with
+// many blocks, where the work-group form's idle waves would cost throughput.
+template <class T>
+__global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs, int nseg,
                                                  int64_t total, int nstrip, int with_mat,
                                                  int with_rhs, const cx<T>* __restrict__ inB,
                                                  const cx<T>* __restrict__ iny,
