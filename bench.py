@@ -28,7 +28,20 @@ Algorithmic model per block, s bytes per complex element of the level
   k_back   read L, P, Q, g, x_{p-1}, x_{p+1}; write x_p.  flops 8 (5/2 m^2 k)
   k_residual (FP64) read A_j (lower), B_j, x_j, y_j; write r_j.
            flops 8 (3 m^2 k)
-Blocks without a neighbour skip the missing terms.
+Blocks without a neighbour skip the missing terms.  Blocks above 64 split
+the elimination into k_potrf_big (Cholesky) and k_trsm_big (substitutions).
+
+Other workloads (one JSON line each, same keys; the default run above is the
+one the contract names):
+  --workload poisson   block 2D Poisson, N=4096, m=256, k=1, eigenvector
+                       right-hand side (residual bound 16 u kappa, see the
+                       design notes)
+  --workload diff      forward solve + adjoint, N=16384, m=64, k=32, c128
+                       (and c64 under forms)
+  --workload batch     512 ragged systems, N = 2 U{128..--batch-half-max}
+  --schedule pcr       Algorithm 1 on the default workload (FP64)
+Profiling runs add --no-autotune (default kernel variants) and --calib-copy
+(a device copy of A of known size for counter calibration).
 """
 from __future__ import annotations
 
