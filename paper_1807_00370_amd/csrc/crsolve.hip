@@ -247,7 +247,7 @@ struct Disp {
             hipLaunchKernelGGL((crs::k_elim_w<T, MT <= 32 ? MT : 32>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
                                (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
-        } else {
+        } else if constexpr (MT <= 32) { // blocks above 32 run the tiled kernels
             constexpr int PW = sizeof(T) == 8 ? 32 : 64;
             hipLaunchKernelGGL((crs::k_elim<T, MT, kNT, PW>), dim3(grid_of(L.total)), dim3(kNT), 0,
                                st, segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
@@ -280,7 +280,7 @@ struct Disp {
         if ((MT == 16 || MT == 32) && variant == 0) {
             hipLaunchKernelGGL((crs::k_back_mf<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
                                segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
-        } else {
+        } else if constexpr (MT <= 32) { // blocks above 32 run the tiled kernels
             constexpr int PW = 32;
             hipLaunchKernelGGL((crs::k_back<T, MT, kNT, PW>), dim3(grid_of(L.total)), dim3(kNT), 0,
                                st, segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X,
@@ -291,9 +291,10 @@ struct Disp {
     static void grad(const Launch& L, const Seg* segs, const void* X, const void* Lam, void* gA,
                      void* gB, hipStream_t st)
     {
-        hipLaunchKernelGGL((crs::k_grad<T, MT, kNT>), dim3(grid_of(L.total)), dim3(kNT), 0, st,
-                           segs + L.seg0, L.nseg, L.total, (const cx<T>*)X, (const cx<T>*)Lam,
-                           (cx<T>*)gA, (cx<T>*)gB);
+        if constexpr (MT <= 32) // blocks above 32 run k_grad_big
+            hipLaunchKernelGGL((crs::k_grad<T, MT, kNT>), dim3(grid_of(L.total)), dim3(kNT), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)X, (const cx<T>*)Lam,
+                               (cx<T>*)gA, (cx<T>*)gB);
     }
 };
 

@@ -13,8 +13,10 @@
 //               form), operands loaded from HBM straight into the MFMA lane
 //               layout; diagonal blocks are written as their lower triangle
 //               only (the Hermitian reading every consumer uses).
-//   k_back_m    w = g - Q x_{p-d} - P x_{p+d} on MFMA, then L^H x = w with one
-//               lane per column.
+//   k_elim_mf   (8 < m <= 32) the same Cholesky, then the substitutions on
+//               MFMA with the inverses of the 16 x 16 diagonal tiles.
+//   k_back_mf   w = g - Q x_{p-d} - P x_{p+d} on MFMA, then L^H x = w tile by
+//               tile on MFMA with the inverse diagonal tiles.
 #pragma once
 
 #include "kernels.hpp"
@@ -894,101 +896,6 @@ __global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* 
                         }
                     }
                 }
-            }
-        }
-    }
-}
-
-// ----------------------------------------------------------------- k_back_m
-
-template <class T, int MT>
-__global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_back_m(const Seg* __restrict__ segs, int nseg,
-                                               int64_t total, const cx<T>* __restrict__ W,
-                                               cx<T>* __restrict__ X,
-                                               const unsigned long long* __restrict__ flags)
-{
-    static_assert(MT % 16 == 0 && MT <= 32, "tile and register limits");
-    using v4 = typename MF<T>::v4;
-    constexpr int NP = MT * (MT + 1) / 2, KS = MT / 4, NT16 = MT / 16, WC = 16;
-    __shared__ cx<T> sL[NP];
-    __shared__ T sInv[MT];
-    __shared__ cx<T> sW[MT * (WC + 1)];
-    const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
-
-    {
-        const int64_t w = blockIdx.x;
-        if (w >= total)
-            return;
-        const Seg& s = segs[find_seg(segs, nseg, w)];
-        const int64_t t = w - s.w0;
-        const int p = s.e0 + (int)t * s.es;
-        const int m = s.m, k = s.k, d = s.d;
-        const bool hasPrev = p - d >= 0, hasNext = p + d < s.n;
-        const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
-        cx<T>* xp = X + s.ox + (s.xo + s.xs * p) * mk;
-        if (flags[s.sys] != kNoFail) {
-            const T nan = T(NAN);
-            for (int e = lane; e < m * k; e += 64)
-                xp[e] = cx<T>{nan, nan};
-            return;
-        }
-        const cx<T>* xm = X + s.ox + (s.xo + s.xs * (p - d)) * mk;
-        const cx<T>* xn = X + s.ox + (s.xo + s.xs * (p + d)) * mk;
-        const cx<T>* L = W + s.oL + t * mm;
-        const cx<T>* P = W + s.oP + t * mm;
-        const cx<T>* Q = W + s.oQ + t * mm;
-        const cx<T>* g = W + s.og + t * mk;
-        __syncthreads();
-        for (int e = lane; e < m * (m + 1) / 2; e += 64)
-            sL[e] = L[e];
-        __syncthreads();
-        for (int c = lane; c < m; c += 64)
-            sInv[c] = sL[c * (c + 1) / 2 + c].i;
-        for (int c0 = 0; c0 < k; c0 += WC) {
-            const int cw = min(WC, k - c0);
-            __syncthreads();
-            for (int ti = 0; ti < NT16; ++ti) {
-                if (16 * ti >= m)
-                    break;
-                v4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-                if (hasPrev)
-                    tile_nn<T, KS>(cr, ci, Q, m, m, 16 * ti, xm + c0, k, cw, 0, m);
-                if (hasNext)
-                    tile_nn<T, KS>(cr, ci, P, m, m, 16 * ti, xn + c0, k, cw, 0, m);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = 16 * ti + MF<T>::row(kr, v);
-                    if (i < m && cc < cw) {
-                        const cx<T> a = g[i * k + c0 + cc];
-                        sW[i * (WC + 1) + cc] = cx<T>{a.r - cr[v], a.i - ci[v]};
-                    }
-                }
-            }
-            __syncthreads();
-            if (lane < cw) {
-                cx<T> x[MT];
-#pragma unroll
-                for (int r = 0; r < MT; ++r)
-                    x[r] = r < m ? sW[r * (WC + 1) + lane] : czero<T>();
-#pragma unroll
-                for (int r = MT - 1; r >= 0; --r) {
-                    if (r < m) {
-                        cx<T> v0 = x[r], v1 = czero<T>();
-#pragma unroll
-                        for (int u = r + 1; u < MT; u += 2) {
-                            if (u < m)
-                                msub_ca(v0, sL[u * (u + 1) / 2 + r], x[u]);
-                            if (u + 1 < MT && u + 1 < m)
-                                msub_ca(v1, sL[(u + 1) * (u + 2) / 2 + r], x[u + 1]);
-                        }
-                        const T iv = sInv[r];
-                        x[r] = cx<T>{(v0.r + v1.r) * iv, (v0.i + v1.i) * iv};
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < MT; ++r)
-                    if (r < m)
-                        xp[r * k + c0 + lane] = x[r];
             }
         }
     }

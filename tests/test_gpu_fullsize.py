@@ -1,0 +1,76 @@
+"""Parity at the full sizes of the precision and differentiation workloads
+(GPU), in the launch configuration bench.py times, against the FP64 oracle.
+
+* precision form: N = 65536, m = 32, k = 16, complex128 inputs, FP32 levels,
+  FP64 tail (<= 8 blocks), FP64 residual refinement to 1e-12 -- the
+  well-conditioned generator and the stated ill variant;
+* differentiation form: N = 16384, m = 64, k = 32, loss
+  sum_j Re tr(W_j^H x_j), gradients for A, B, y in complex128 and complex64.
+
+Tolerances are those of the smaller parity tests: 1e-11 on x (FP64 and
+refined), 1e-10 on the FP64 gradients (one more solve and an outer product),
+1e-3 on the complex64 gradients (kappa * 6e-8 with kappa <= 10 and the
+reduction depth).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_00370_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tdev(cuda_ok):
+    import torch
+    from paper_1807_00370_amd import _lib
+    _lib.load()
+    return torch, torch.device("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("ill", [False, True])
+def test_refine_full_size(tdev, ill):
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import Solver
+    print("case refine full N=65536 m=32 k=16 ill=%s" % ill, flush=True)
+    s = W.random_hpd(**W.LARGE, seed=W.config_seed(2), ill=ill)
+    A, B, y = (torch.from_numpy(v).to(dev) for v in (s.A, s.B, s.y))
+    sol = Solver([s.N], [s.m], [s.k], precision="fp32_refine", device=dev, rtol=1e-12,
+                 max_refine=30, fp64_tail_blocks=8)
+    sol.set_graphs(True)
+    x = sol.factor_solve(A, B, y).cpu().numpy()
+    rec = sol.info_host()[0]
+    assert int(rec["status"]) == 0 and int(rec["fp64_fallback"]) == 0
+    res = oracle.rel_residual(s.A, s.B, x, s.y)
+    assert res <= 1e-12
+    assert abs(float(rec["rel_residual"]) - res) <= 0.1 * res + 1e-16
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert io["status"] == 0
+    assert _rel(x, xo) <= 1e-11
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_adjoint_full_size(tdev, dt):
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import cr_solve
+    print("case adjoint full N=16384 m=64 k=32 %s" % dt, flush=True)
+    dtype = torch.complex128 if dt == "c128" else torch.complex64
+    s = W.random_hpd(**W.DIFF, seed=W.config_seed(4), with_W=True)
+    A, B, y, Wt = (torch.from_numpy(v).to(dev).to(dtype) for v in (s.A, s.B, s.y, s.W))
+    for t in (A, B, y):
+        t.requires_grad_(True)
+    x = cr_solve(A, B, y)
+    (Wt.conj() * x).real.sum().backward()
+    xo, _ = oracle.solve_cr(s.A, s.B, s.y)
+    lam, _ = oracle.solve_cr(s.A, s.B, s.W)
+    gA, gB = oracle.backward(xo, lam)
+    tol = 1e-10 if dt == "c128" else 1e-3
+    assert _rel(x.detach().cpu().numpy().astype(np.complex128), xo) <= (1e-11 if dt == "c128" else 2e-4)
+    assert _rel(A.grad.cpu().numpy(), gA) <= tol
+    assert _rel(B.grad.cpu().numpy(), gB) <= tol
+    assert _rel(y.grad.cpu().numpy(), lam) <= tol
