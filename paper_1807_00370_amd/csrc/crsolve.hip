@@ -237,11 +237,12 @@ struct Disp {
     template <int MT>
     static void elim(const Launch& L, const Seg* segs, const void* inA, const void* inB,
                      const void* iny, void* W, unsigned long long* flags, int mat, int rhs,
-                     hipStream_t st, int variant)
+                     hipStream_t st, int variant, int nsplit)
     {
         if ((MT == 16 || MT == 32) && variant == 0) {
-            hipLaunchKernelGGL((crs::k_elim_mf<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+            hipLaunchKernelGGL((crs::k_elim_mf<T, (MT == 16 || MT == 32) ? MT : 16>),
+                               dim3((unsigned)(L.total * nsplit)), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, nsplit, (const cx<T>*)inA,
                                (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else if (MT <= 32 && variant == 0) {
             hipLaunchKernelGGL((crs::k_elim_w<T, MT <= 32 ? MT : 32>), dim3((unsigned)L.total), dim3(64), 0, st,
@@ -355,6 +356,17 @@ constexpr int64_t kTrsmStripBlocks = 256;
 // Grid of the tiled kernels: a multiple of 8 work-groups (see xcd_item).
 unsigned grid8(int64_t items) { return (unsigned)((items + 7) / 8 * 8); }
 
+// Levels of the one-wave MFMA classes (8 < m <= 32) with few blocks are bound
+// by one block's chain of dependent steps, not by throughput.  There the
+// elimination splits each block's strips over up to kTailWaves / blocks
+// waves, and launches of at most kTailBlocks blocks form the reduced system
+// one wave per 16 x 16 output tile.  kTailWaves is the GPU's wave slots at
+// the two waves per SIMD that k_elim_mf runs at.
+constexpr int64_t kTailWaves = 2048;
+constexpr int64_t kTailBlocks = 1024;
+
+bool mf_class(int cls) { return cls == 2 || cls == 3; }
+
 template <class T>
 void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const void* y, int mat,
               int rhs)
@@ -388,7 +400,13 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
     }
     Timed tm(c.p, KID_ELIM, c.st, L.cls, L.f64);
     const int v = c.p->var[0][L.cls][L.f64];
-#define CALL(MT) Disp<T>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st, v)
+    int nsplit = 1;
+    if (mf_class(L.cls) && v == 0) {
+        const BigDims b = big_dims(c.p, L);
+        const int nst = (mat ? 2 * b.S : 0) + (rhs ? b.K16 : 0);
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nst, kTailWaves / L.total));
+    }
+#define CALL(MT) Disp<T>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st, v, nsplit)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
@@ -404,7 +422,16 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
         const BigDims b = big_dims(c.p, L);
         const int nt = (mat ? b.T32 * (b.T32 + 1) / 2 + b.T32 * b.T32 : 0) + (rhs ? b.T32 * b.K32 : 0);
         if (nt > 0)
-            hipLaunchKernelGGL((crs::k_reduce_big<T>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 2>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, mat, rhs, (const cx<T>*)inA,
+                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+        return;
+    }
+    if (mf_class(L.cls) && L.total <= kTailBlocks) {
+        const BigDims b = big_dims(c.p, L);
+        const int nt = (mat ? b.S * (b.S + 1) / 2 + b.S * b.S : 0) + (rhs ? b.S * b.K16 : 0);
+        if (nt > 0)
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 1>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
                                c.dsegs + L.seg0, L.nseg, L.total, nt, mat, rhs, (const cx<T>*)inA,
                                (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
         return;

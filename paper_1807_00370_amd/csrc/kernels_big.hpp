@@ -613,10 +613,12 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
 
 // ------------------------------------------------------------ k_reduce_big
 
-// Tiles of a kept block (T32 = ceil(m / 32)): with_mat gives the
-// T32 (T32 + 1) / 2 lower tiles of A' and the T32^2 tiles of B', with_rhs the
-// T32 ceil(k / 32) tiles of y' after them.
-template <class T>
+// One wave per output tile of TT = 16 TW rows and columns of a kept block
+// (NT = ceil(m / TT)): with_mat gives the NT (NT + 1) / 2 lower tiles of A'
+// and the NT^2 tiles of B', with_rhs the NT ceil(k / TT) tiles of y' after
+// them.  TW = 2 serves the blocks above 32; TW = 1 the levels of smaller
+// blocks with too few blocks to fill the GPU one wave per block.
+template <class T, int TW>
 __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int ntile, int with_mat,
                                                    int with_rhs, const cx<T>* __restrict__ inA,
@@ -642,7 +644,8 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
     const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
     if ((flags[s.sys] >> 40) <= (unsigned long long)s.level)
         return; // the level's elimination broke down: stop this system
-    const int T32 = (m + 31) >> 5, nV = T32 * (T32 + 1) / 2, nF = T32 * T32;
+    constexpr int TT = 16 * TW;
+    const int NT = (m + TT - 1) / TT, nV = NT * (NT + 1) / 2, nF = NT * NT;
     int kind, ti, tj;
     if (with_mat && u < nV + nF) {
         if (u < nV) {
@@ -652,16 +655,16 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
         } else {
             kind = 1;
             u -= nV;
-            ti = u / T32;
-            tj = u % T32;
+            ti = u / NT;
+            tj = u % NT;
             if (!hasR || r + d >= n)
                 return;
         }
     } else {
         if (with_mat)
             u -= nV + nF;
-        const int Tk = (k + 31) >> 5;
-        if (!with_rhs || u >= T32 * Tk)
+        const int Tk = (k + TT - 1) / TT;
+        if (!with_rhs || u >= NT * Tk)
             return;
         kind = 2;
         ti = u / Tk;
@@ -670,22 +673,22 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
     const cx<T>* Pl = W + s.oP + tl * mm;
     const cx<T>* Qr = W + s.oQ + tr * mm;
     const cx<T>* Pr = W + s.oP + tr * mm;
-    const int i0 = 32 * ti, j0 = 32 * tj;
-    v4 cr[2][2], ci[2][2];
-    zero_acc<T, 2, 2>(cr, ci);
+    const int i0 = TT * ti, j0 = TT * tj;
+    v4 cr[TW][TW], ci[TW][TW];
+    zero_acc<T, TW, TW>(cr, ci);
     if (kind == 0) {
         if (hasL)
-            wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Pl + i0, 1, m, m - i0},
+            wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Pl + i0, 1, m, m - i0},
                                              WOp<T>{Pl + j0, 1, m, m - j0}, m);
         if (hasR)
-            wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Qr + i0, 1, m, m - i0},
+            wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{Qr + j0, 1, m, m - j0}, m);
         const cx<T>* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < TW; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < TW; ++b)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), j = j0 + 16 * b + cc;
@@ -698,13 +701,13 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                     }
                 }
     } else if (kind == 1) {
-        wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Pr + i0, 1, m, m - i0},
+        wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Pr + i0, 1, m, m - i0},
                                          WOp<T>{Qr + j0, 1, m, m - j0}, m);
         cx<T>* Fo = W + s.oBo + oi * mm;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < TW; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < TW; ++b)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), j = j0 + 16 * b + cc;
@@ -715,17 +718,17 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
         const cx<T>* gl = W + s.og + tl * mk;
         const cx<T>* gr = W + s.og + tr * mk;
         if (hasL)
-            wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Pl + i0, 1, m, m - i0},
+            wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Pl + i0, 1, m, m - i0},
                                              WOp<T>{gl + j0, 1, k, k - j0}, m);
         if (hasR)
-            wave_mm<T, 2, 2, true, false, 2>(cr, ci, WOp<T>{Qr + i0, 1, m, m - i0},
+            wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{gr + j0, 1, k, k - j0}, m);
         const cx<T>* yq = iny + s.oy + q * mk;
         cx<T>* vo = W + s.oyo + oi * mk;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < TW; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < TW; ++b)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), c = j0 + 16 * b + cc;

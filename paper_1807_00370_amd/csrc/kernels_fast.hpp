@@ -389,11 +389,18 @@ __device__ __forceinline__ void inverse_tiles_lds(cx<T>* sL, int m)
 // MF::row(kr, v) of its column, which is the right operand of contraction
 // step v when the left operand supplies column MF::row(kr, v), so the
 // products chain through the accumulators.  Right-hand sides are read from
-// memory straight into that layout, the first strip before the Cholesky and
-// each next strip while the current one is solved.
+// memory straight into that layout, each next strip while the current one is
+// solved.
+//
+// nsplit waves share a block: wave sp solves strips sp, sp + nsplit, ...
+// Each of them factors the block itself (a few microseconds of latency,
+// no cross-wave synchronisation); wave 0 alone stores L and raises the
+// breakdown flag.  Levels with few blocks use nsplit > 1 to shorten the
+// chain of strips that one wave walks through.
 template <class T, int MT>
 __global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs, int nseg,
-                                                   int64_t total, const cx<T>* __restrict__ inA,
+                                                   int64_t total, int nsplit,
+                                                   const cx<T>* __restrict__ inA,
                                                    const cx<T>* __restrict__ inB,
                                                    const cx<T>* __restrict__ iny,
                                                    cx<T>* __restrict__ W,
@@ -408,7 +415,8 @@ __global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs,
     __shared__ cx<T> sL[NS]; // packed L, later the D tiles
     __shared__ int sFail;
     const int lane = threadIdx.x, kr = lane >> 4, cc = lane & 15;
-    const int64_t w = blockIdx.x;
+    const int64_t w = blockIdx.x / nsplit;
+    const int sp = (int)(blockIdx.x - w * nsplit);
     if (w >= total)
         return;
     const Seg& s = segs[find_seg(segs, nseg, w)];
@@ -499,10 +507,12 @@ __global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs,
         }
         if (lane == 0)
             sFail = fail;
-        if (lane == 0 && sFail)
-            atomicMin(&flags[s.sys], fail_key(s.level, s.ob0 + s.obs * p));
-        for (int e = lane; e < np; e += 64)
-            Lg[e] = sL[e];
+        if (sp == 0) {
+            if (lane == 0 && sFail)
+                atomicMin(&flags[s.sys], fail_key(s.level, s.ob0 + s.obs * p));
+            for (int e = lane; e < np; e += 64)
+                Lg[e] = sL[e];
+        }
     } else {
         for (int e = lane; e < np; e += 64)
             sL[e] = Lg[e];
@@ -524,18 +534,18 @@ __global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs,
         for (int v = 0; v < 4; ++v)
             aD[I][v] = sL[I * 256 + cc * 16 + MF<T>::row(kr, v)];
 
-    if (nst > 0)
-        CRS_LOAD_STRIP(0, gn);
+    if (sp < nst)
+        CRS_LOAD_STRIP(sp, gn);
 #pragma unroll 1
-    for (int st = 0; st < nst; ++st) {
+    for (int st = sp; st < nst; st += nsplit) {
         cx<T> g[S][4];
 #pragma unroll
         for (int I = 0; I < S; ++I)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 g[I][v] = gn[I][v];
-        if (st + 1 < nst)
-            CRS_LOAD_STRIP(st + 1, gn);
+        if (st + nsplit < nst)
+            CRS_LOAD_STRIP(st + nsplit, gn);
         // X_0 = D_0 G_0
         v4 x0r = {0, 0, 0, 0}, x0i = {0, 0, 0, 0};
 #pragma unroll

@@ -202,6 +202,48 @@ def test_backward_matches_oracle(torch_dev, N, m, k, dt):
     assert _rel(y.grad.cpu().numpy(), lam) <= tol
 
 
+@pytest.mark.parametrize("N,m,k", [(8192, 12, 3), (6000, 24, 20)])
+def test_mf_throughput_and_tail_levels(torch_dev, N, m, k):
+    """8 < m <= 32 with levels above and below the block counts where the
+    elimination splits a block's strips over several waves and the reduced
+    system is formed one wave per output tile (k > 16 in the second case)."""
+    torch, dev = torch_dev
+    print("case mf levels N=%d m=%d k=%d" % (N, m, k), flush=True)
+    s = W.random_hpd(N, m, k, 7300 + m)
+    x, info = _solve(torch, dev, s)
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert info == io
+    assert _rel(x, xo) <= TOL64
+    assert oracle.rel_residual(s.A, s.B, x, s.y) <= RES64
+
+
+def test_mf_ragged_mixed_regimes(torch_dev):
+    """One launch per level holds a system with thousands of blocks and small
+    ones of the same class: the split and per-tile forms take effect at the
+    same level for all of them; every system equals its own oracle solve."""
+    torch, dev = torch_dev
+    from paper_1807_00370_amd.solver import Solver
+    print("case mf ragged mixed regimes", flush=True)
+    shapes = [(4500, 32, 16), (40, 20, 5), (3, 30, 33), (700, 9, 2), (5000, 14, 1)]
+    systems = [W.random_hpd(N, m, k, 7400 + i) for i, (N, m, k) in enumerate(shapes)]
+    A = np.concatenate([s.A.ravel() for s in systems])
+    B = np.concatenate([s.B.ravel() for s in systems])
+    y = np.concatenate([s.y.ravel() for s in systems])
+    sol = Solver([s.N for s in systems], [s.m for s in systems], [s.k for s in systems],
+                 device=dev)
+    At, Bt, yt = (torch.from_numpy(v).to(dev) for v in (A, B, y))
+    x = sol.factor_solve(At, Bt, yt).cpu().numpy()
+    x2 = sol.solve(yt).cpu().numpy()
+    assert np.array_equal(x, x2)
+    off = 0
+    for i, s in enumerate(systems):
+        xs = x[off:off + s.y.size].reshape(s.y.shape)
+        off += s.y.size
+        xo, io = oracle.solve_cr(s.A, s.B, s.y)
+        assert _info(sol.info_host()[i]) == io
+        assert _rel(xs, xo) <= TOL64, i
+
+
 def test_large_single_system_full_size(torch_dev):
     """N = 65536, m = 32, k = 16, complex128: every entry against the oracle
     and the FP64 residual."""
