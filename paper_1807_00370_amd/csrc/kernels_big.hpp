@@ -1,7 +1,7 @@
 // Kernels of a reduction level for block sizes 64 < m <= 256 (the block 2D
 // Poisson workload has m = 256).  A block no longer fits in LDS, so every
-// step is cut into 16 x 16 MFMA tiles (real-pair 4-multiply complex form)
-// whose operands stream from L2:
+// step is cut into 16 x 16 MFMA tiles whose operands stream from L2 (the
+// streaming products in the three-multiplication complex form, Acc3):
 //
 //   k_potrf_big   one work-group per eliminated block: blocked left-looking
 //                 Cholesky L_p = chol(A_p) by 16-column panels.  The panel
@@ -109,6 +109,115 @@ __device__ __forceinline__ void wave_mm(typename MF<T>::v4 (&cr)[RM][RN],
                     ci[i][j] = MF<T>::mma(ar, bi, ci[i][j]);
                     ci[i][j] = MF<T>::mma(ai, br, ci[i][j]);
                 }
+    };
+    load(xa0, yb0, 0);
+    for (int g = 0; g < ng; g += 2) {
+        if (g + 1 < ng)
+            load(xa1, yb1, g + 1);
+        comp(xa0, yb0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (g + 1 < ng) {
+            if (g + 2 < ng)
+                load(xa0, yb0, g + 2);
+            comp(xa1, yb1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// Accumulators of the three-multiplication (3M) complex product: with
+// a = op(A), b = op(B) split into real and imaginary parts,
+//   t1 += Re a Re b,  t2 += Im a Im b,  t3 += (Re a + Im a)(Re b + Im b),
+// and the product is Re = t1 - t2, Im = t3 - t1 - t2: three real MFMAs per
+// complex contraction step instead of four.  The real part is the 4M one;
+// the imaginary part carries an absolute error of a few units of roundoff
+// times sum_t (|Re a| + |Im a|)(|Re b| + |Im b|) (normwise stable, not
+// componentwise; Higham, Accuracy and Stability of Numerical Algorithms,
+// Section 23.2.4).  For real data t2 = 0 and t3 = t1 bit for bit, so the
+// imaginary part is exactly zero.
+template <class T, int RM, int RN>
+struct Acc3 {
+    using v4 = typename MF<T>::v4;
+    v4 t1[RM][RN], t2[RM][RN], t3[RM][RN];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+                t1[i][j] = t2[i][j] = t3[i][j] = v4{0, 0, 0, 0};
+    }
+    __device__ __forceinline__ T re(int i, int j, int v) const { return t1[i][j][v] - t2[i][j][v]; }
+    __device__ __forceinline__ T im(int i, int j, int v) const
+    {
+        return t3[i][j][v] - t1[i][j][v] - t2[i][j][v];
+    }
+};
+
+// acc += opA(A) opB(B) in the 3M form, operands as in wave_mm.
+template <class T, int RM, int RN, bool CA, bool CB, int G>
+__device__ __forceinline__ void wave_mm3(Acc3<T, RM, RN>& acc, const WOp<T> A, const WOp<T> B,
+                                         int kd)
+{
+    const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+    const int ng = (kd + 4 * G - 1) / (4 * G);
+    if (ng <= 0)
+        return;
+    const cx<T>* pa[RM];
+    const cx<T>* pb[RN];
+    bool oa[RM], ob[RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+        const int o = 16 * i + cc;
+        oa[i] = o < A.no;
+        pa[i] = A.p + ((oa[i] ? o : 0) * A.so + kr * A.st);
+    }
+#pragma unroll
+    for (int j = 0; j < RN; ++j) {
+        const int o = 16 * j + cc;
+        ob[j] = o < B.no;
+        pb[j] = B.p + ((ob[j] ? o : 0) * B.so + kr * B.st);
+    }
+    const int sa = 4 * A.st, sb = 4 * B.st;
+    cx<T> xa0[RM][G], yb0[RN][G], xa1[RM][G], yb1[RN][G];
+    auto load = [&](cx<T>(&xa)[RM][G], cx<T>(&yb)[RN][G], int g) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int ks = g * G + u;
+            const bool ok = 4 * ks + kr < kd;
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+                xa[i][u] = (ok && oa[i]) ? pa[i][ks * sa] : czero<T>();
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+                yb[j][u] = (ok && ob[j]) ? pb[j][ks * sb] : czero<T>();
+        }
+    };
+    auto comp = [&](const cx<T>(&xa)[RM][G], const cx<T>(&yb)[RN][G]) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            T ar[RM], ai[RM], as[RM], br[RN], bi[RN], bs[RN];
+#pragma unroll
+            for (int i = 0; i < RM; ++i) {
+                ar[i] = xa[i][u].r;
+                ai[i] = CA ? -xa[i][u].i : xa[i][u].i;
+                as[i] = ar[i] + ai[i];
+            }
+#pragma unroll
+            for (int j = 0; j < RN; ++j) {
+                br[j] = yb[j][u].r;
+                bi[j] = CB ? -yb[j][u].i : yb[j][u].i;
+                bs[j] = br[j] + bi[j];
+            }
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+                for (int j = 0; j < RN; ++j) {
+                    acc.t1[i][j] = MF<T>::mma(ar[i], br[j], acc.t1[i][j]);
+                    acc.t2[i][j] = MF<T>::mma(ai[i], bi[j], acc.t2[i][j]);
+                    acc.t3[i][j] = MF<T>::mma(as[i], bs[j], acc.t3[i][j]);
+                }
+        }
     };
     load(xa0, yb0, 0);
     for (int g = 0; g < ng; g += 2) {
@@ -235,16 +344,16 @@ __global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs,
         // panel column I: S_R = A[R][I] - L[R][<I] L[I][<I]^H for R >= I (the
         // Hermitian reading of A: lower triangle of the diagonal tile only)
         for (int R = I + wv; R < S; R += 4) {
-            v4 cr[1][1], ci[1][1];
-            zero_acc<T, 1, 1>(cr, ci);
-            wave_mm<T, 1, 1, false, true, 4>(cr, ci, WOp<T>{Lg + (int64_t)16 * R * m, m, 1, m - 16 * R},
-                                             WOp<T>{Lg + (int64_t)c0 * m, m, 1, m - c0}, c0);
+            Acc3<T, 1, 1> acc;
+            acc.zero();
+            wave_mm3<T, 1, 1, false, true, 4>(acc, WOp<T>{Lg + (int64_t)16 * R * m, m, 1, m - 16 * R},
+                                              WOp<T>{Lg + (int64_t)c0 * m, m, 1, m - c0}, c0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * R + MF<T>::row(kr, v), j = c0 + cc;
                 if (i < m && j < m && (R > I || j <= i)) {
                     const cx<T> a = Ap[(int64_t)i * m + j];
-                    Lg[(int64_t)i * m + j] = cx<T>{a.r - cr[0][0][v], a.i - ci[0][0][v]};
+                    Lg[(int64_t)i * m + j] = cx<T>{a.r - acc.re(0, 0, v), a.i - acc.im(0, 0, v)};
                 }
             }
         }
@@ -318,16 +427,16 @@ __global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs,
         __syncthreads();
         // tiles below the diagonal: L[R][I] = S_R D_I^H, in place
         for (int R = I + 1 + wv; R < S; R += 4) {
-            v4 cr[1][1], ci[1][1];
-            zero_acc<T, 1, 1>(cr, ci);
-            wave_mm<T, 1, 1, false, true, 4>(cr, ci,
-                                             WOp<T>{Lg + (int64_t)16 * R * m + c0, m, 1, m - 16 * R},
-                                             WOp<T>{Dg + I * 256, 16, 1, 16}, min(16, m - c0));
+            Acc3<T, 1, 1> acc;
+            acc.zero();
+            wave_mm3<T, 1, 1, false, true, 4>(acc,
+                                              WOp<T>{Lg + (int64_t)16 * R * m + c0, m, 1, m - 16 * R},
+                                              WOp<T>{Dg + I * 256, 16, 1, 16}, min(16, m - c0));
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * R + MF<T>::row(kr, v), j = c0 + cc;
                 if (i < m && j < m)
-                    Lg[(int64_t)i * m + j] = cx<T>{cr[0][0][v], ci[0][0][v]};
+                    Lg[(int64_t)i * m + j] = cx<T>{acc.re(0, 0, v), acc.im(0, 0, v)};
             }
         }
         __syncthreads();
@@ -579,33 +688,33 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
     const cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
     for (int I = 0; I < S; ++I) {
         const int r0 = 16 * I;
-        v4 cr[1][1], ci[1][1];
-        zero_acc<T, 1, 1>(cr, ci);
-        wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{Lg + (int64_t)r0 * m, m, 1, m - r0},
-                                          WOp<T>{out + c0, 1, ldo, nc}, r0);
+        Acc3<T, 1, 1> acc;
+        acc.zero();
+        wave_mm3<T, 1, 1, false, false, 4>(acc, WOp<T>{Lg + (int64_t)r0 * m, m, 1, m - r0},
+                                           WOp<T>{out + c0, 1, ldo, nc}, r0);
         // w = G_I - acc stays in the accumulator layout: register v of lane
         // (kr, cc) holds row MF::row(kr, v) of column cc, which is the right
         // operand of contraction step v once the left operand D_I supplies
         // column MF::row(kr, v) of its row cc
-        v4 xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+        Acc3<T, 1, 1> x;
+        x.zero();
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int rr = MF<T>::row(kr, v), r = r0 + rr;
             cx<T> g = (r < m && cc < nc) ? G[r * gr + (c0 + cc) * gc] : czero<T>();
             if (src == 0)
                 g.i = -g.i;
-            const T br = g.r - cr[0][0][v], bi = g.i - ci[0][0][v];
+            const T br = g.r - acc.re(0, 0, v), bi = g.i - acc.im(0, 0, v);
             const cx<T> a = Dg[I * 256 + cc * 16 + rr];
-            xr = MF<T>::mma(a.r, br, xr);
-            xr = MF<T>::mma(-a.i, bi, xr);
-            xi = MF<T>::mma(a.r, bi, xi);
-            xi = MF<T>::mma(a.i, br, xi);
+            x.t1[0][0] = MF<T>::mma(a.r, br, x.t1[0][0]);
+            x.t2[0][0] = MF<T>::mma(a.i, bi, x.t2[0][0]);
+            x.t3[0][0] = MF<T>::mma(a.r + a.i, br + bi, x.t3[0][0]);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = r0 + MF<T>::row(kr, v);
             if (r < m && cc < nc)
-                out[(int64_t)r * ldo + c0 + cc] = cx<T>{xr[v], xi[v]};
+                out[(int64_t)r * ldo + c0 + cc] = cx<T>{x.re(0, 0, v), x.im(0, 0, v)};
         }
         __syncthreads(); // the rows just stored are the next tiles' operands
     }
@@ -674,14 +783,14 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
     const cx<T>* Qr = W + s.oQ + tr * mm;
     const cx<T>* Pr = W + s.oP + tr * mm;
     const int i0 = TT * ti, j0 = TT * tj;
-    v4 cr[TW][TW], ci[TW][TW];
-    zero_acc<T, TW, TW>(cr, ci);
+    Acc3<T, TW, TW> acc;
+    acc.zero();
     if (kind == 0) {
         if (hasL)
-            wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Pl + i0, 1, m, m - i0},
+            wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Pl + i0, 1, m, m - i0},
                                              WOp<T>{Pl + j0, 1, m, m - j0}, m);
         if (hasR)
-            wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Qr + i0, 1, m, m - i0},
+            wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{Qr + j0, 1, m, m - j0}, m);
         const cx<T>* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
@@ -694,14 +803,14 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), j = j0 + 16 * b + cc;
                     if (i < m && j <= i) {
                         const cx<T> x = Aq[i * m + j];
-                        cx<T> o{x.r - cr[a][b][v], x.i - ci[a][b][v]};
+                        cx<T> o{x.r - acc.re(a, b, v), x.i - acc.im(a, b, v)};
                         if (i == j)
                             o.i = T(0);
                         Vo[i * m + j] = o;
                     }
                 }
     } else if (kind == 1) {
-        wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Pr + i0, 1, m, m - i0},
+        wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Pr + i0, 1, m, m - i0},
                                          WOp<T>{Qr + j0, 1, m, m - j0}, m);
         cx<T>* Fo = W + s.oBo + oi * mm;
 #pragma unroll
@@ -712,16 +821,16 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                 for (int v = 0; v < 4; ++v) {
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), j = j0 + 16 * b + cc;
                     if (i < m && j < m)
-                        Fo[i * m + j] = cx<T>{-cr[a][b][v], -ci[a][b][v]};
+                        Fo[i * m + j] = cx<T>{-acc.re(a, b, v), -acc.im(a, b, v)};
                 }
     } else {
         const cx<T>* gl = W + s.og + tl * mk;
         const cx<T>* gr = W + s.og + tr * mk;
         if (hasL)
-            wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Pl + i0, 1, m, m - i0},
+            wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Pl + i0, 1, m, m - i0},
                                              WOp<T>{gl + j0, 1, k, k - j0}, m);
         if (hasR)
-            wave_mm<T, TW, TW, true, false, 4 / TW>(cr, ci, WOp<T>{Qr + i0, 1, m, m - i0},
+            wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{gr + j0, 1, k, k - j0}, m);
         const cx<T>* yq = iny + s.oy + q * mk;
         cx<T>* vo = W + s.oyo + oi * mk;
@@ -734,7 +843,7 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), c = j0 + 16 * b + cc;
                     if (i < m && c < k) {
                         const cx<T> x = yq[i * k + c];
-                        vo[i * k + c] = cx<T>{x.r - cr[a][b][v], x.i - ci[a][b][v]};
+                        vo[i * k + c] = cx<T>{x.r - acc.re(a, b, v), x.i - acc.im(a, b, v)};
                     }
                 }
     }
@@ -800,21 +909,21 @@ __global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs,
     for (int v = 0; v < 4; ++v)
         aD[v] = own ? Dg[wv * 256 + MF<T>::row(kr, v) * 16 + cc] : czero<T>();
     // phase A
-    v4 cr[1][1], ci[1][1];
-    zero_acc<T, 1, 1>(cr, ci);
+    Acc3<T, 1, 1> acc;
+    acc.zero();
     if (own && hasPrev)
-        wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{Q + (int64_t)r0 * m, m, 1, m - r0},
-                                          WOp<T>{xm + c0, 1, k, nc}, m);
+        wave_mm3<T, 1, 1, false, false, 4>(acc, WOp<T>{Q + (int64_t)r0 * m, m, 1, m - r0},
+                                           WOp<T>{xm + c0, 1, k, nc}, m);
     if (own && hasNext)
-        wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{P + (int64_t)r0 * m, m, 1, m - r0},
-                                          WOp<T>{xn + c0, 1, k, nc}, m);
+        wave_mm3<T, 1, 1, false, false, 4>(acc, WOp<T>{P + (int64_t)r0 * m, m, 1, m - r0},
+                                           WOp<T>{xn + c0, 1, k, nc}, m);
     v4 wr, wi;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int r = r0 + MF<T>::row(kr, v);
         const cx<T> gv = (own && r < m && cc < nc) ? g[r * k + c0 + cc] : czero<T>();
-        wr[v] = gv.r - cr[0][0][v];
-        wi[v] = gv.i - ci[0][0][v];
+        wr[v] = gv.r - acc.re(0, 0, v);
+        wi[v] = gv.i - acc.im(0, 0, v);
     }
     // operand of the update at step I: A(i, t) = conj(L[16 I + t][r0 + i]),
     // lane (cc, kr) holds t = 4 s + kr for the contraction steps s

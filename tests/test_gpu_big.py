@@ -189,6 +189,9 @@ def test_poisson_small_matches_oracle(tdev):
     assert info == io == dict(status=0, level=-1, block=-1)
     assert _rel(x, xo) <= TOL64
     assert _rel(x, s.y / s.meta["lam"]) <= TOL64
+    # real data: the imaginary parts of every product cancel exactly, in the
+    # 3M form too (t3 and t1 are the same real products)
+    assert np.all(x.imag == 0.0)
 
 
 def test_poisson_full_size_closed_form(tdev):
