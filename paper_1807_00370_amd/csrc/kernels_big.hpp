@@ -1,4 +1,4 @@
-// Kernels of a reduction level for block sizes 64 < m <= 256 (the block 2D
+// Kernels of a reduction level for block sizes 32 < m <= 256 (the block 2D
 // Poisson workload has m = 256).  A block no longer fits in LDS, so every
 // step is cut into 16 x 16 MFMA tiles whose operands stream from L2 (the
 // streaming products in the three-multiplication complex form, Acc3):
@@ -16,7 +16,9 @@
 //                 L \ G for the three operands of Eq. (Formulas).
 //   k_reduce_big  one wave per (kept block, 32 x 32 tile) of the reduced
 //                 system A' = A_q - P_l^H P_l - Q_r^H Q_r (lower triangle),
-//                 B' = -P_r^H Q_r, y' = y_q - P_l^H g_l - Q_r^H g_r.
+//                 B' = -P_r^H Q_r, y' = y_q - P_l^H g_l - Q_r^H g_r; with
+//                 16 x 16 tiles it also serves the levels of m <= 32 that
+//                 hold few blocks.
 //   k_back_big    one work-group per (eliminated block, 16-column strip of
 //                 x_p), one wave per row tile: blocked back substitution of
 //                 L^H x_p = g_p - Q_p x_{p-d} - P_p x_{p+d}.
