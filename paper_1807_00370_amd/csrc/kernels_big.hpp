@@ -127,35 +127,6 @@ __device__ __forceinline__ void wave_mm(typename MF<T>::v4 (&cr)[RM][RN],
     }
 }
 
-// Accumulators of the three-multiplication (3M) complex product: with
-// a = op(A), b = op(B) split into real and imaginary parts,
-//   t1 += Re a Re b,  t2 += Im a Im b,  t3 += (Re a + Im a)(Re b + Im b),
-// and the product is Re = t1 - t2, Im = t3 - t1 - t2: three real MFMAs per
-// complex contraction step instead of four.  The real part is the 4M one;
-// the imaginary part carries an absolute error of a few units of roundoff
-// times sum_t (|Re a| + |Im a|)(|Re b| + |Im b|) (normwise stable, not
-// componentwise; Higham, Accuracy and Stability of Numerical Algorithms,
-// Section 23.2.4).  For real data t2 = 0 and t3 = t1 bit for bit, so the
-// imaginary part is exactly zero.
-template <class T, int RM, int RN>
-struct Acc3 {
-    using v4 = typename MF<T>::v4;
-    v4 t1[RM][RN], t2[RM][RN], t3[RM][RN];
-    __device__ __forceinline__ void zero()
-    {
-#pragma unroll
-        for (int i = 0; i < RM; ++i)
-#pragma unroll
-            for (int j = 0; j < RN; ++j)
-                t1[i][j] = t2[i][j] = t3[i][j] = v4{0, 0, 0, 0};
-    }
-    __device__ __forceinline__ T re(int i, int j, int v) const { return t1[i][j][v] - t2[i][j][v]; }
-    __device__ __forceinline__ T im(int i, int j, int v) const
-    {
-        return t3[i][j][v] - t1[i][j][v] - t2[i][j][v];
-    }
-};
-
 // acc += opA(A) opB(B) in the 3M form, operands as in wave_mm.
 template <class T, int RM, int RN, bool CA, bool CB, int G>
 __device__ __forceinline__ void wave_mm3(Acc3<T, RM, RN>& acc, const WOp<T> A, const WOp<T> B,

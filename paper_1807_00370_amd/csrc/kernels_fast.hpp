@@ -86,6 +86,35 @@ __device__ __forceinline__ float rsqrt_nr(float d)
 // from hoisting every load of the tile to the top (register pressure).
 constexpr int kGroup = 4;
 
+// Accumulators of the three-multiplication (3M) complex product: with
+// a = op(A), b = op(B) split into real and imaginary parts,
+//   t1 += Re a Re b,  t2 += Im a Im b,  t3 += (Re a + Im a)(Re b + Im b),
+// and the product is Re = t1 - t2, Im = t3 - t1 - t2: three real MFMAs per
+// complex contraction step instead of four.  The real part is the 4M one;
+// the imaginary part carries an absolute error of a few units of roundoff
+// times sum_t (|Re a| + |Im a|)(|Re b| + |Im b|) (normwise stable, not
+// componentwise; Higham, Accuracy and Stability of Numerical Algorithms,
+// Section 23.2.4).  For real data t2 = 0 and t3 = t1 bit for bit, so the
+// imaginary part is exactly zero.
+template <class T, int RM, int RN>
+struct Acc3 {
+    using v4 = typename MF<T>::v4;
+    v4 t1[RM][RN], t2[RM][RN], t3[RM][RN];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+                t1[i][j] = t2[i][j] = t3[i][j] = v4{0, 0, 0, 0};
+    }
+    __device__ __forceinline__ T re(int i, int j, int v) const { return t1[i][j][v] - t2[i][j][v]; }
+    __device__ __forceinline__ T im(int i, int j, int v) const
+    {
+        return t3[i][j][v] - t1[i][j][v] - t2[i][j][v];
+    }
+};
+
 // (cr, ci) += X^H Y on the 16 x 16 tile with rows cx0.. (columns of X) and
 // columns cy0.. (columns of Y); X, Y row-major, contraction over their first
 // kd rows.  Out-of-range rows and columns read as zero.
@@ -164,6 +193,44 @@ __device__ __forceinline__ void tile_nn(typename MF<T>::v4& cr, typename MF<T>::
             cr = MF<T>::mma(-a.i, b.i, cr);
             ci = MF<T>::mma(a.r, b.i, ci);
             ci = MF<T>::mma(a.i, b.r, ci);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// acc += X Y as tile_nn, in the 3M form.
+template <class T, int KS>
+__device__ __forceinline__ void tile_nn3(Acc3<T, 1, 1>& acc, const cx<T>* __restrict__ X, int ldx,
+                                         int nrx, int rx0, const cx<T>* __restrict__ Y, int ldy,
+                                         int ncy, int cy0, int kd)
+{
+    constexpr int G = KS < kGroup ? KS : kGroup, NG = KS / G;
+    const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+    const int ar = rx0 + cc, by = cy0 + cc;
+    const bool okx = ar < nrx, oky = by < ncy;
+    const cx<T>* xb = X + (ar * ldx + kr);
+    const cx<T>* yq = Y + (kr * ldy + by);
+    const int sy = 4 * ldy;
+    cx<T> xa[2][G], yb[2][G];
+    auto load = [&](int g, int b) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int ks = g * G + u, t = 4 * ks + kr;
+            xa[b][u] = (t < kd && okx) ? xb[4 * ks] : czero<T>();
+            yb[b][u] = (t < kd && oky) ? yq[ks * sy] : czero<T>();
+        }
+    };
+    load(0, 0);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        if (g + 1 < NG)
+            load(g + 1, (g + 1) & 1);
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const cx<T> a = xa[g & 1][u], b = yb[g & 1][u];
+            acc.t1[0][0] = MF<T>::mma(a.r, b.r, acc.t1[0][0]);
+            acc.t2[0][0] = MF<T>::mma(a.i, b.i, acc.t2[0][0]);
+            acc.t3[0][0] = MF<T>::mma(a.r + a.i, b.r + b.i, acc.t3[0][0]);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -637,6 +704,20 @@ __device__ __forceinline__ void mma_hn(typename MF<T>::v4& cr, typename MF<T>::v
     }
 }
 
+// acc += A^H B for operand tiles A and B in the 3M form.
+template <class T, int KS>
+__device__ __forceinline__ void mma_hn3(Acc3<T, 1, 1>& acc, const OpTile<T, KS>& A,
+                                        const OpTile<T, KS>& B)
+{
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const T ar = A.v[s].r, ai = -A.v[s].i, br = B.v[s].r, bi = B.v[s].i;
+        acc.t1[0][0] = MF<T>::mma(ar, br, acc.t1[0][0]);
+        acc.t2[0][0] = MF<T>::mma(ai, bi, acc.t2[0][0]);
+        acc.t3[0][0] = MF<T>::mma(ar + ai, br + bi, acc.t3[0][0]);
+    }
+}
+
 // Reduced system for a kept block q with eliminated neighbours l, r:
 //   A'_q = A_q - P_l^H P_l - Q_r^H Q_r,  B'_q = -P_r^H Q_r,
 //   y'_q = y_q - P_l^H g_l - Q_r^H g_r.
@@ -679,13 +760,13 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
     // right-hand side columns beyond the first 16 are handled in later chunks
     const int kc0 = with_rhs ? (k < 16 ? k : 16) : 0;
     Tile X[NT16], G;
-    v4 vr[NV], vi[NV], yr[NT16], yi[NT16];
+    Acc3<T, 1, 1> av[NV], ay[NT16];
 #pragma unroll
     for (int i = 0; i < NV; ++i)
-        vr[i] = vi[i] = z4;
+        av[i].zero();
 #pragma unroll
     for (int i = 0; i < NT16; ++i)
-        yr[i] = yi[i] = z4;
+        ay[i].zero();
 
     // phase 1: P_l^H P_l and P_l^H g_l;  phase 2: Q_r^H Q_r and Q_r^H g_r
 #pragma unroll
@@ -705,12 +786,12 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
             for (int i = 0, v = 0; i < NT16; ++i)
 #pragma unroll
                 for (int j = 0; j <= i; ++j, ++v)
-                    mma_hn<T, MT / 4>(vr[v], vi[v], X[i], X[j]);
+                    mma_hn3<T, MT / 4>(av[v], X[i], X[j]);
         }
         if (kc0) {
 #pragma unroll
             for (int i = 0; i < NT16; ++i)
-                mma_hn<T, MT / 4>(yr[i], yi[i], X[i], G);
+                mma_hn3<T, MT / 4>(ay[i], X[i], G);
         }
     }
     if (with_mat) {
@@ -725,7 +806,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
                     const int a = 16 * i + MF<T>::row(kr, u), b = 16 * j + cc;
                     if (a < m && b <= a) {
                         const cx<T> x = Aq[a * m + b];
-                        cx<T> o{x.r - vr[v][u], x.i - vi[v][u]};
+                        cx<T> o{x.r - av[v].re(0, 0, u), x.i - av[v].im(0, 0, u)};
                         if (a == b)
                             o.i = T(0);
                         Vo[a * m + b] = o;
@@ -742,7 +823,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
                 const int a = 16 * i + MF<T>::row(kr, u), c = cc;
                 if (a < m && c < kc0) {
                     const cx<T> x = yq[a * k + c];
-                    yo[a * k + c] = cx<T>{x.r - yr[i][u], x.i - yi[i][u]};
+                    yo[a * k + c] = cx<T>{x.r - ay[i].re(0, 0, u), x.i - ay[i].im(0, 0, u)};
                 }
             }
     }
@@ -757,13 +838,14 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
         for (int i = 0; i < NT16; ++i)
 #pragma unroll
             for (int j = 0; j < NT16; ++j) {
-                v4 fr = z4, fi = z4;
-                mma_hn<T, MT / 4>(fr, fi, Pt[i], X[j]);
+                Acc3<T, 1, 1> af;
+                af.zero();
+                mma_hn3<T, MT / 4>(af, Pt[i], X[j]);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int a = 16 * i + MF<T>::row(kr, u), b = 16 * j + cc;
                     if (a < m && b < m)
-                        Fo[a * m + b] = cx<T>{-fr[u], -fi[u]};
+                        Fo[a * m + b] = cx<T>{-af.re(0, 0, u), -af.im(0, 0, u)};
                 }
             }
     }
@@ -774,25 +856,26 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
         for (int c0 = 16; c0 < k; c0 += 16) {
 #pragma unroll
             for (int i = 0; i < NT16; ++i) {
-                v4 ar = z4, ai = z4;
+                Acc3<T, 1, 1> ac;
+                ac.zero();
                 if (hasL) {
                     Tile A1, G1;
                     A1.load(Pl, m, m, 16 * i, m);
                     G1.load(gl, k, k, c0, m);
-                    mma_hn<T, MT / 4>(ar, ai, A1, G1);
+                    mma_hn3<T, MT / 4>(ac, A1, G1);
                 }
                 if (hasR) {
                     Tile A1, G1;
                     A1.load(Qr, m, m, 16 * i, m);
                     G1.load(gr, k, k, c0, m);
-                    mma_hn<T, MT / 4>(ar, ai, A1, G1);
+                    mma_hn3<T, MT / 4>(ac, A1, G1);
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int a = 16 * i + MF<T>::row(kr, u), c = c0 + cc;
                     if (a < m && c < k) {
                         const cx<T> x = yq[a * k + c];
-                        yo[a * k + c] = cx<T>{x.r - ar[u], x.i - ai[u]};
+                        yo[a * k + c] = cx<T>{x.r - ac.re(0, 0, u), x.i - ac.im(0, 0, u)};
                     }
                 }
             }
@@ -981,17 +1064,18 @@ __global__ __launch_bounds__(64, 2) void k_back_mf(const Seg* __restrict__ segs,
         T wr[S][4], wi[S][4];
 #pragma unroll
         for (int I = 0; I < S; ++I) {
-            v4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+            Acc3<T, 1, 1> acc;
+            acc.zero();
             if (hasPrev)
-                tile_nn<T, KS>(cr, ci, Q, m, m, 16 * I, xm + c0, k, cw, 0, m);
+                tile_nn3<T, KS>(acc, Q, m, m, 16 * I, xm + c0, k, cw, 0, m);
             if (hasNext)
-                tile_nn<T, KS>(cr, ci, P, m, m, 16 * I, xn + c0, k, cw, 0, m);
+                tile_nn3<T, KS>(acc, P, m, m, 16 * I, xn + c0, k, cw, 0, m);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = 16 * I + MF<T>::row(kr, v);
                 const cx<T> gv = (r < m && cc < cw) ? g[r * k + c0 + cc] : czero<T>();
-                wr[I][v] = gv.r - cr[v];
-                wi[I][v] = gv.i - ci[v];
+                wr[I][v] = gv.r - acc.re(0, 0, v);
+                wi[I][v] = gv.i - acc.im(0, 0, v);
             }
         }
         // bottom tile first: x_{S-1} = D_{S-1}^H w_{S-1}
