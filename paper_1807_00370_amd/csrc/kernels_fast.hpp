@@ -613,36 +613,50 @@ __global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs,
                 g[I][v] = gn[I][v];
         if (st + nsplit < nst)
             CRS_LOAD_STRIP(st + nsplit, gn);
-        // X_0 = D_0 G_0
-        v4 x0r = {0, 0, 0, 0}, x0i = {0, 0, 0, 0};
+        // X_0 = D_0 G_0 (3M products, combined before they chain on)
+        v4 x0r, x0i;
+        {
+            Acc3<T, 1, 1> p;
+            p.zero();
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const cx<T> a = aD[0][v], b = g[0][v];
-            x0r = MF<T>::mma(a.r, b.r, x0r);
-            x0r = MF<T>::mma(-a.i, b.i, x0r);
-            x0i = MF<T>::mma(a.r, b.i, x0i);
-            x0i = MF<T>::mma(a.i, b.r, x0i);
+            for (int v = 0; v < 4; ++v) {
+                const cx<T> a = aD[0][v], b = g[0][v];
+                p.t1[0][0] = MF<T>::mma(a.r, b.r, p.t1[0][0]);
+                p.t2[0][0] = MF<T>::mma(a.i, b.i, p.t2[0][0]);
+                p.t3[0][0] = MF<T>::mma(a.r + a.i, b.r + b.i, p.t3[0][0]);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                x0r[v] = p.re(0, 0, v);
+                x0i[v] = p.im(0, 0, v);
+            }
         }
         v4 x1r = {0, 0, 0, 0}, x1i = {0, 0, 0, 0};
         if (S == 2) {
             // T = L_10 X_0, then X_1 = D_1 (G_1 - T)
-            v4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+            Acc3<T, 1, 1> p;
+            p.zero();
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const cx<T> a = aL[v];
-                tr = MF<T>::mma(a.r, x0r[v], tr);
-                tr = MF<T>::mma(-a.i, x0i[v], tr);
-                ti = MF<T>::mma(a.r, x0i[v], ti);
-                ti = MF<T>::mma(a.i, x0r[v], ti);
+                p.t1[0][0] = MF<T>::mma(a.r, x0r[v], p.t1[0][0]);
+                p.t2[0][0] = MF<T>::mma(a.i, x0i[v], p.t2[0][0]);
+                p.t3[0][0] = MF<T>::mma(a.r + a.i, x0r[v] + x0i[v], p.t3[0][0]);
             }
+            Acc3<T, 1, 1> q;
+            q.zero();
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const cx<T> a = aD[S - 1][v];
-                const T br = g[S - 1][v].r - tr[v], bi = g[S - 1][v].i - ti[v];
-                x1r = MF<T>::mma(a.r, br, x1r);
-                x1r = MF<T>::mma(-a.i, bi, x1r);
-                x1i = MF<T>::mma(a.r, bi, x1i);
-                x1i = MF<T>::mma(a.i, br, x1i);
+                const T br = g[S - 1][v].r - p.re(0, 0, v), bi = g[S - 1][v].i - p.im(0, 0, v);
+                q.t1[0][0] = MF<T>::mma(a.r, br, q.t1[0][0]);
+                q.t2[0][0] = MF<T>::mma(a.i, bi, q.t2[0][0]);
+                q.t3[0][0] = MF<T>::mma(a.r + a.i, br + bi, q.t3[0][0]);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                x1r[v] = q.re(0, 0, v);
+                x1i[v] = q.im(0, 0, v);
             }
         }
         const int src = st < nP ? 0 : (st < nP + nQ ? 1 : 2);
