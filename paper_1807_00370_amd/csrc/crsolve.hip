@@ -360,8 +360,9 @@ unsigned grid8(int64_t items) { return (unsigned)((items + 7) / 8 * 8); }
 // by one block's chain of dependent steps, not by throughput.  There the
 // elimination splits each block's strips over up to kTailWaves / blocks
 // waves, and launches of at most kTailBlocks blocks form the reduced system
-// one wave per 16 x 16 output tile.  kTailWaves is the GPU's wave slots at
-// the two waves per SIMD that k_elim_mf runs at.
+// one wave per 16 x 16 output tile.  Both thresholds were measured on the
+// N = 65536, m = 32 workload (kTailWaves 1024 .. 8192, kTailBlocks 512 ..
+// 4096); kTailWaves is about the wave slots of the GPU's 1024 SIMDs.
 constexpr int64_t kTailWaves = 2048;
 constexpr int64_t kTailBlocks = 1024;
 

@@ -82,7 +82,7 @@ struct Seg {
     int64_t oL, oP, oQ, og;   // per eliminated block (index t)
     int64_t oAo, oBo, oyo;    // reduced system
     int64_t ox;               // unknowns of the system
-    int64_t oD;               // inverse diagonal tiles (block sizes above 64)
+    int64_t oD;               // inverse diagonal tiles (block sizes above 32)
 };
 
 constexpr unsigned long long kNoFail = ~0ull;

@@ -76,6 +76,24 @@ __device__ __forceinline__ float rsqrt_nr(float d)
     return r * fmaf(-0.5f * d * r, r, 1.5f);
 }
 
+// Value of x in lane l (uniform l) through the scalar registers.
+__device__ __forceinline__ float lane_bcast(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_bcast(double x, int l)
+{
+    const long long v = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <class T>
+__device__ __forceinline__ cx<T> lane_bcast(const cx<T> x, int l)
+{
+    return cx<T>{lane_bcast(x.r, l), lane_bcast(x.i, l)};
+}
+
 // MFMA 16x16x4 lane layout (wave64, checked on gfx950): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register v of lane l
 // holds D[row][l % 16] with row = 4 (l / 16) + v for the f32 instruction and
@@ -459,13 +477,17 @@ __device__ __forceinline__ void inverse_tiles_lds(cx<T>* sL, int m)
 // memory straight into that layout, each next strip while the current one is
 // solved.
 //
+// The register budget is held to three waves per SIMD (168 VGPRs for FP64,
+// m = 32, no spills), which hides more of each block's latency than the
+// 196 registers the compiler would take on its own.
+//
 // nsplit waves share a block: wave sp solves strips sp, sp + nsplit, ...
 // Each of them factors the block itself (a few microseconds of latency,
 // no cross-wave synchronisation); wave 0 alone stores L and raises the
 // breakdown flag.  Levels with few blocks use nsplit > 1 to shorten the
 // chain of strips that one wave walks through.
 template <class T, int MT>
-__global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs, int nseg,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_elim_mf(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int nsplit,
                                                    const cx<T>* __restrict__ inA,
                                                    const cx<T>* __restrict__ inB,
@@ -534,31 +556,32 @@ __global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs,
             sL[e] = Ap[r * m + c];
         }
         __syncthreads();
-        // left-looking Cholesky, one row per lane (as in k_elim_w)
+        // left-looking Cholesky, one row per lane: lane c holds row c of L,
+        // whose finished entries reach every lane through the scalar
+        // registers (no LDS round trip or barrier per column)
         cx<T> a[MT];
         const int rl = lane < m ? lane : 0;
 #pragma unroll
         for (int u = 0; u < MT; ++u)
             a[u] = (u <= rl) ? sL[rl * (rl + 1) / 2 + u] : czero<T>();
-        __syncthreads();
         bool fail = false;
 #pragma unroll
         for (int c = 0; c < MT; ++c) {
             if (c < m) {
                 cx<T> s0 = czero<T>(), s1 = czero<T>();
-                // dot product in chunks of 16 terms (bounds the LDS reads in
-                // flight next to the 2 MT registers of the row)
+                // dot product in chunks of 8 terms (bounds the scalar
+                // registers of the broadcast row entries in flight)
 #pragma unroll
                 for (int u = 0; u + 1 < c; u += 2) {
-                    msub_cb(s0, a[u], sL[c * (c + 1) / 2 + u]);
-                    msub_cb(s1, a[u + 1], sL[c * (c + 1) / 2 + u + 1]);
-                    if ((u & 15) == 14)
+                    msub_cb(s0, a[u], lane_bcast(a[u], c));
+                    msub_cb(s1, a[u + 1], lane_bcast(a[u + 1], c));
+                    if ((u & 7) == 6)
                         __builtin_amdgcn_sched_barrier(0);
                 }
                 if (c & 1)
-                    msub_cb(s0, a[c - 1], sL[c * (c + 1) / 2 + c - 1]);
+                    msub_cb(s0, a[c - 1], lane_bcast(a[c - 1], c));
                 const cx<T> v{a[c].r + s0.r + s1.r, a[c].i + s0.i + s1.i};
-                const T dg = __shfl(v.r, c);
+                const T dg = lane_bcast(v.r, c);
                 const T inv = rsqrt_nr(dg);
                 const T sq = dg * inv;
                 fail |= !(dg > T(0));
@@ -566,12 +589,17 @@ __global__ __launch_bounds__(64, 2) void k_elim_mf(const Seg* __restrict__ segs,
                     a[c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
                 else
                     a[c] = cx<T>{v.r * inv, v.i * inv};
-                if (lane >= c && lane < m)
-                    sL[lane * (lane + 1) / 2 + c] = a[c];
-                __syncthreads();
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+        __syncthreads(); // every lane has read its row of A from LDS
+        if (lane < m) {
+#pragma unroll
+            for (int u = 0; u < MT; ++u)
+                if (u <= lane)
+                    sL[lane * (lane + 1) / 2 + u] = a[u];
+        }
+        __syncthreads();
         if (lane == 0)
             sFail = fail;
         if (sp == 0) {
