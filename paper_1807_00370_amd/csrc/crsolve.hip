@@ -353,6 +353,10 @@ BigDims big_dims(const crsolve_plan* p, const Launch& L)
 // work-group form with its shorter chain and shared L tiles.
 constexpr int64_t kTrsmStripBlocks = 256;
 
+// Tiled Cholesky launches of at most this many blocks (one per CU) run
+// work-groups of eight waves.
+constexpr int64_t kPotrfWideBlocks = 256;
+
 // Grid of the tiled kernels: a multiple of 8 work-groups (see xcd_item).
 unsigned grid8(int64_t items) { return (unsigned)((items + 7) / 8 * 8); }
 
@@ -379,7 +383,10 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
         const BigDims b = big_dims(c.p, L);
         if (mat) {
             Timed tm(c.p, KID_POTRF, c.st, L.cls, L.f64);
-            hipLaunchKernelGGL((crs::k_potrf_big<T>), dim3((unsigned)L.total), dim3(256), 0, c.st,
+            // levels with at most one block per CU spread the panel tiles over
+            // eight waves instead of four
+            const unsigned nthr = L.total <= kPotrfWideBlocks ? 512 : 256;
+            hipLaunchKernelGGL((crs::k_potrf_big<T>), dim3((unsigned)L.total), dim3(nthr), 0, c.st,
                                c.dsegs + L.seg0, L.nseg, L.total, (const cx<T>*)inA, (cx<T>*)c.ws,
                                c.flags);
         }

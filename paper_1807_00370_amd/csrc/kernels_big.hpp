@@ -3,7 +3,8 @@
 // step is cut into 16 x 16 MFMA tiles whose operands stream from L2 (the
 // streaming products in the three-multiplication complex form, Acc3):
 //
-//   k_potrf_big   one work-group per eliminated block: blocked left-looking
+//   k_potrf_big   one work-group (four or eight waves) per eliminated
+//                 block: blocked left-looking
 //                 Cholesky L_p = chol(A_p) by 16-column panels.  The panel
 //                 update L[R][<I] L[I][<I]^H runs on MFMA, each 16 x 16
 //                 diagonal tile is factored in registers (one row per lane)
@@ -288,15 +289,17 @@ __device__ __forceinline__ void wave_lds_sync()
 // ------------------------------------------------------------- k_potrf_big
 
 template <class T>
-__global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs, int nseg,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_potrf_big(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, const cx<T>* __restrict__ inA,
                                                    cx<T>* __restrict__ W,
                                                    unsigned long long* __restrict__ flags)
 {
     using v4 = typename MF<T>::v4;
-    __shared__ cx<T> sT[16 * 17]; // diagonal tile of L (row-major, leading dimension 17)
+    __shared__ cx<T> sT[16 * 17]; // diagonal tile S_I (row-major, leading dimension 17)
+    __shared__ cx<T> sD[16 * 17]; // D_I for the tiles below the diagonal (leading dimension 17)
     __shared__ int sFail;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, kr = lane >> 4, cc = lane & 15;
+    const int nw = blockDim.x >> 6;
     const int64_t w = blockIdx.x;
     if (w >= total)
         return;
@@ -316,7 +319,7 @@ __global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs,
         const int c0 = 16 * I;
         // panel column I: S_R = A[R][I] - L[R][<I] L[I][<I]^H for R >= I (the
         // Hermitian reading of A: lower triangle of the diagonal tile only)
-        for (int R = I + wv; R < S; R += 4) {
+        for (int R = I + wv; R < S; R += nw) {
             Acc3<T, 1, 1> acc;
             acc.zero();
             wave_mm3<T, 1, 1, false, true, 4>(acc, WOp<T>{Lg + (int64_t)16 * R * m, m, 1, m - 16 * R},
@@ -326,15 +329,20 @@ __global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs,
                 const int i = 16 * R + MF<T>::row(kr, v), j = c0 + cc;
                 if (i < m && j < m && (R > I || j <= i)) {
                     const cx<T> a = Ap[(int64_t)i * m + j];
-                    Lg[(int64_t)i * m + j] = cx<T>{a.r - acc.re(0, 0, v), a.i - acc.im(0, 0, v)};
+                    const cx<T> o{a.r - acc.re(0, 0, v), a.i - acc.im(0, 0, v)};
+                    if (R == I) // the diagonal tile goes to wave 0 through LDS
+                        sT[(i - c0) * 17 + (j - c0)] = o;
+                    else
+                        Lg[(int64_t)i * m + j] = o;
                 }
             }
         }
         __syncthreads();
         // diagonal tile (wave 0): lane r & 15 keeps row r in registers;
-        // left-looking Cholesky that publishes each finished column to LDS,
-        // where later columns read the rows of L by broadcast; then lane r
-        // forms column r of D = L_II^{-1} by forward substitution
+        // left-looking Cholesky in which lane c broadcasts the finished
+        // entries of row c through the scalar registers; then lane r forms
+        // column r of D = L_II^{-1} by forward substitution, reading the
+        // rows of L the same way
         if (wv == 0) {
             const int r = lane & 15, gi = c0 + r;
             const bool real = gi < m;
@@ -342,7 +350,7 @@ __global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs,
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 if (real)
-                    a[u] = u <= r ? Lg[(int64_t)gi * m + c0 + u] : czero<T>();
+                    a[u] = u <= r ? sT[r * 17 + u] : czero<T>();
                 else
                     a[u] = u == r ? cx<T>{T(1), T(0)} : czero<T>();
                 if (u == r)
@@ -354,13 +362,13 @@ __global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs,
                 cx<T> s0 = a[c], s1 = czero<T>();
 #pragma unroll
                 for (int u = 0; u + 1 < c; u += 2) {
-                    msub_cb(s0, a[u], sT[c * 17 + u]);
-                    msub_cb(s1, a[u + 1], sT[c * 17 + u + 1]);
+                    msub_cb(s0, a[u], lane_bcast(a[u], c));
+                    msub_cb(s1, a[u + 1], lane_bcast(a[u + 1], c));
                 }
                 if (c & 1)
-                    msub_cb(s0, a[c - 1], sT[c * 17 + c - 1]);
+                    msub_cb(s0, a[c - 1], lane_bcast(a[c - 1], c));
                 const cx<T> sv{s0.r + s1.r, s0.i + s1.i};
-                const T dg = __shfl(sv.r, c);
+                const T dg = lane_bcast(sv.r, c);
                 const T inv = rsqrt_nr(dg);
                 const T sq = dg * inv;
                 fail |= (c0 + c < m) && !(dg > T(0));
@@ -368,9 +376,6 @@ __global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs,
                     a[c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
                 else if (r > c)
                     a[c] = cx<T>{sv.r * inv, sv.i * inv};
-                if (lane < 16)
-                    sT[r * 17 + c] = a[c];
-                wave_lds_sync();
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (lane < 16 && real) {
@@ -385,26 +390,28 @@ __global__ __launch_bounds__(256) void k_potrf_big(const Seg* __restrict__ segs,
                 cx<T> v = q == r ? cx<T>{T(1), T(0)} : czero<T>();
 #pragma unroll
                 for (int u = 0; u < q; ++u)
-                    msub(v, sT[q * 17 + u], z[u]);
-                const T iq = sT[q * 17 + q].i;
+                    msub(v, lane_bcast(a[u], q), z[u]);
+                const T iq = lane_bcast(a[q].i, q);
                 z[q] = cx<T>{v.r * iq, v.i * iq};
             }
             if (lane < 16) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q)
+                for (int q = 0; q < 16; ++q) {
                     Dg[I * 256 + q * 16 + r] = z[q];
+                    sD[q * 17 + r] = z[q];
+                }
             }
             if (lane == 0 && fail)
                 sFail = 1;
         }
         __syncthreads();
         // tiles below the diagonal: L[R][I] = S_R D_I^H, in place
-        for (int R = I + 1 + wv; R < S; R += 4) {
+        for (int R = I + 1 + wv; R < S; R += nw) {
             Acc3<T, 1, 1> acc;
             acc.zero();
             wave_mm3<T, 1, 1, false, true, 4>(acc,
                                               WOp<T>{Lg + (int64_t)16 * R * m + c0, m, 1, m - 16 * R},
-                                              WOp<T>{Dg + I * 256, 16, 1, 16}, min(16, m - c0));
+                                              WOp<T>{sD, 17, 1, 16}, min(16, m - c0));
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * R + MF<T>::row(kr, v), j = c0 + cc;
