@@ -428,10 +428,21 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
     const int v = c.p->var[1][L.cls][L.f64];
     if (L.cls == kBig || (tiled(L.cls) && v == 0)) {
         const BigDims b = big_dims(c.p, L);
-        const int nt = (mat ? b.T32 * (b.T32 + 1) / 2 + b.T32 * b.T32 : 0) + (rhs ? b.T32 * b.K32 : 0);
+        // blocks above 64: A' and B' from LDS-staged 64 x 64 tiles, y' in
+        // 32 x 32 tiles (for m <= 64 the per-wave tiles are faster: the
+        // LDS form would run one or two work-groups per block)
+        const bool staged = mat && L.cls == kBig;
+        if (staged) {
+            const int T64 = (b.S + 3) / 4, nm = T64 * (T64 + 1) / 2 + T64 * T64;
+            hipLaunchKernelGGL((crs::k_reduce_lds<T>), dim3(grid8(L.total * nm)), dim3(256), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nm, (const cx<T>*)inA,
+                               (cx<T>*)c.ws, c.flags);
+        }
+        const int mt = mat && !staged ? 1 : 0;
+        const int nt = (mt ? b.T32 * (b.T32 + 1) / 2 + b.T32 * b.T32 : 0) + (rhs ? b.T32 * b.K32 : 0);
         if (nt > 0)
             hipLaunchKernelGGL((crs::k_reduce_big<T, 2>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nt, mat, rhs, (const cx<T>*)inA,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, mt, rhs, (const cx<T>*)inA,
                                (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
         return;
     }

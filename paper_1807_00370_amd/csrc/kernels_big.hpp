@@ -20,6 +20,8 @@
 //                 B' = -P_r^H Q_r, y' = y_q - P_l^H g_l - Q_r^H g_r; with
 //                 16 x 16 tiles it also serves the levels of m <= 32 that
 //                 hold few blocks.
+//   k_reduce_lds  A' and B' for blocks above 64: one work-group of four
+//                 waves per 64 x 64 tile, operand panels staged in LDS.
 //   k_back_big    one work-group per (eliminated block, 16-column strip of
 //                 x_p), one wave per row tile: blocked back substitution of
 //                 L^H x_p = g_p - Q_p x_{p-d} - P_p x_{p+d}.
@@ -825,6 +827,183 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                         const cx<T> x = yq[i * k + c];
                         vo[i * k + c] = cx<T>{x.r - acc.re(a, b, v), x.i - acc.im(a, b, v)};
                     }
+                }
+    }
+}
+
+// ------------------------------------------------------------ k_reduce_lds
+
+// The matrix part of the reduced system (A' lower tiles, B') for blocks above
+// 32 with the operand panels staged in LDS: one work-group of four waves per
+// (kept block, 64 x 64 tile); wave (a, b) owns the 32 x 32 quarter at rows
+// 32 a, columns 32 b of the tile.  For each 16-row panel of the contraction
+// the work-group loads 16 x 64 of the left and of the right operand once
+// (every element then feeds 32 output rows or columns instead of 16 in
+// k_reduce_big) and the waves run their 3M products from LDS; the next panel
+// is fetched into registers while the current one is consumed (two LDS
+// buffers, one barrier per panel).  Items per kept block: the
+// NT (NT + 1) / 2 lower tiles of A', then the NT^2 tiles of B' (NT =
+// ceil(m / 64)).  The right-hand-side tiles y' run in k_reduce_big.
+template <class T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_reduce_lds(const Seg* __restrict__ segs, int nseg,
+                                                    int64_t total, int ntile,
+                                                    const cx<T>* __restrict__ inA,
+                                                    cx<T>* __restrict__ W,
+                                                    const unsigned long long* __restrict__ flags)
+{
+    constexpr int KP = 16, LD = 65;
+    __shared__ cx<T> sA[2][KP * LD], sB[2][KP * LD];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, kr = lane >> 4, cc = lane & 15;
+    const int wa = wv >> 1, wb = wv & 1;
+    const int64_t li = xcd_item();
+    const int64_t w = li / ntile;
+    int u = (int)(li - w * ntile);
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int q = s.k0 + (int)t * s.ks;
+    const int m = s.m, d = s.d, n = s.n;
+    const int l = q - d, r = q + d;
+    const bool hasL = l >= 0, hasR = r < n;
+    const int64_t tl = hasL ? (l - s.e0) / s.es : 0, tr = hasR ? (r - s.e0) / s.es : 0;
+    const int64_t oi = s.out_by_pos ? q : t;
+    const int64_t mm = (int64_t)m * m;
+    if ((flags[s.sys] >> 40) <= (unsigned long long)s.level)
+        return; // the level's elimination broke down: stop this system
+    const int NT = (m + 63) >> 6, nV = NT * (NT + 1) / 2, nF = NT * NT;
+    int kind, ti, tj;
+    if (u < nV) {
+        kind = 0;
+        ti = tri_row(u);
+        tj = u - ti * (ti + 1) / 2;
+    } else if (u < nV + nF) {
+        kind = 1;
+        u -= nV;
+        ti = u / NT;
+        tj = u % NT;
+        if (!hasR || r + d >= n)
+            return;
+    } else {
+        return;
+    }
+    const cx<T>* Pl = W + s.oP + tl * mm;
+    const cx<T>* Qr = W + s.oQ + tr * mm;
+    const cx<T>* Pr = W + s.oP + tr * mm;
+    const int i0 = 64 * ti, j0 = 64 * tj;
+    // products: A' tiles sum P_l^H P_l (hasL) and Q_r^H Q_r (hasR); B' tiles
+    // are P_r^H Q_r
+    const int npr = kind == 0 ? (hasL ? 1 : 0) + (hasR ? 1 : 0) : 1;
+    const int nkp = (m + KP - 1) / KP, npan = npr * nkp;
+    // quarters above the diagonal of a diagonal tile hold no output
+    const bool live = !(kind == 0 && ti == tj && wb > wa);
+    // thread tid moves elements e = tid + 256 e4 of a 16 x 64 panel: row
+    // e / 64, column e % 64
+    cx<T> ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define CRS_PANEL_LOAD(pn)                                                                         \
+    do {                                                                                           \
+        const int pr_ = (pn) / nkp, t0_ = ((pn) - pr_ * nkp) * KP;                                  \
+        const cx<T>* X_ = kind == 1 ? Pr : ((hasL && pr_ == 0) ? Pl : Qr);                          \
+        const cx<T>* Y_ = kind == 1 ? Qr : X_;                                                      \
+        const int row_ = tid >> 6, col_ = tid & 63;                                                 \
+        const bool oa_ = i0 + col_ < m, ob_ = j0 + col_ < m;                                        \
+        const cx<T>* xa_ = X_ + (int64_t)(t0_ + row_) * m + i0 + col_;                              \
+        const cx<T>* yb_ = Y_ + (int64_t)(t0_ + row_) * m + j0 + col_;                              \
+        const int64_t st_ = 4 * (int64_t)m;                                                         \
+        ra0 = (t0_ + row_ < m && oa_) ? xa_[0] : czero<T>();                                        \
+        ra1 = (t0_ + row_ + 4 < m && oa_) ? xa_[st_] : czero<T>();                                  \
+        ra2 = (t0_ + row_ + 8 < m && oa_) ? xa_[2 * st_] : czero<T>();                              \
+        ra3 = (t0_ + row_ + 12 < m && oa_) ? xa_[3 * st_] : czero<T>();                             \
+        rb0 = (t0_ + row_ < m && ob_) ? yb_[0] : czero<T>();                                        \
+        rb1 = (t0_ + row_ + 4 < m && ob_) ? yb_[st_] : czero<T>();                                  \
+        rb2 = (t0_ + row_ + 8 < m && ob_) ? yb_[2 * st_] : czero<T>();                              \
+        rb3 = (t0_ + row_ + 12 < m && ob_) ? yb_[3 * st_] : czero<T>();                             \
+    } while (0)
+#define CRS_PANEL_STORE(b)                                                                         \
+    do {                                                                                           \
+        const int o_ = (tid >> 6) * LD + (tid & 63);                                                \
+        sA[b][o_] = ra0;                                                                            \
+        sA[b][o_ + 4 * LD] = ra1;                                                                   \
+        sA[b][o_ + 8 * LD] = ra2;                                                                   \
+        sA[b][o_ + 12 * LD] = ra3;                                                                  \
+        sB[b][o_] = rb0;                                                                            \
+        sB[b][o_ + 4 * LD] = rb1;                                                                   \
+        sB[b][o_ + 8 * LD] = rb2;                                                                   \
+        sB[b][o_ + 12 * LD] = rb3;                                                                  \
+    } while (0)
+    Acc3<T, 2, 2> acc;
+    acc.zero();
+    if (npan > 0) {
+        CRS_PANEL_LOAD(0);
+        CRS_PANEL_STORE(0);
+    }
+    __syncthreads();
+    for (int pn = 0; pn < npan; ++pn) {
+        const int b = pn & 1;
+        if (pn + 1 < npan)
+            CRS_PANEL_LOAD(pn + 1);
+        if (live) {
+#pragma unroll
+            for (int ks = 0; ks < KP / 4; ++ks) {
+                const int row = 4 * ks + kr;
+                T ar[2], ai[2], as[2], br[2], bi[2], bs[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const cx<T> x = sA[b][row * LD + 32 * wa + 16 * i + cc];
+                    ar[i] = x.r;
+                    ai[i] = -x.i; // conj: the left operand is X^H
+                    as[i] = ar[i] + ai[i];
+                    const cx<T> y = sB[b][row * LD + 32 * wb + 16 * i + cc];
+                    br[i] = y.r;
+                    bi[i] = y.i;
+                    bs[i] = br[i] + bi[i];
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc.t1[i][j] = MF<T>::mma(ar[i], br[j], acc.t1[i][j]);
+                        acc.t2[i][j] = MF<T>::mma(ai[i], bi[j], acc.t2[i][j]);
+                        acc.t3[i][j] = MF<T>::mma(as[i], bs[j], acc.t3[i][j]);
+                    }
+            }
+        }
+        if (pn + 1 < npan)
+            CRS_PANEL_STORE(b ^ 1);
+        __syncthreads();
+    }
+#undef CRS_PANEL_LOAD
+#undef CRS_PANEL_STORE
+    const int ib = i0 + 32 * wa, jb = j0 + 32 * wb;
+    if (kind == 0) {
+        const cx<T>* Aq = inA + s.oA + q * mm;
+        cx<T>* Vo = W + s.oAo + oi * mm;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = ib + 16 * a + MF<T>::row(kr, v), j = jb + 16 * b + cc;
+                    if (i < m && j <= i) {
+                        const cx<T> x = Aq[(int64_t)i * m + j];
+                        cx<T> o{x.r - acc.re(a, b, v), x.i - acc.im(a, b, v)};
+                        if (i == j)
+                            o.i = T(0);
+                        Vo[(int64_t)i * m + j] = o;
+                    }
+                }
+    } else {
+        cx<T>* Fo = W + s.oBo + oi * mm;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = ib + 16 * a + MF<T>::row(kr, v), j = jb + 16 * b + cc;
+                    if (i < m && j < m)
+                        Fo[(int64_t)i * m + j] = cx<T>{-acc.re(a, b, v), -acc.im(a, b, v)};
                 }
     }
 }
