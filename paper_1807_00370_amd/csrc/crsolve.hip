@@ -386,9 +386,14 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
             // levels with at most one block per CU spread the panel tiles over
             // eight waves instead of four
             const unsigned nthr = L.total <= kPotrfWideBlocks ? 512 : 256;
-            hipLaunchKernelGGL((crs::k_potrf_big<T>), dim3((unsigned)L.total), dim3(nthr), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, (const cx<T>*)inA, (cx<T>*)c.ws,
-                               c.flags);
+            if (L.cls == kBig)
+                hipLaunchKernelGGL((crs::k_potrf_big<T, false>), dim3((unsigned)L.total), dim3(nthr), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                                   (cx<T>*)c.ws, c.flags);
+            else
+                hipLaunchKernelGGL((crs::k_potrf_big<T, true>), dim3((unsigned)L.total), dim3(nthr), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                                   (cx<T>*)c.ws, c.flags);
         }
         const int ns = (mat ? 2 * b.S : 0) + (rhs ? b.K16 : 0);
         if (ns > 0) {
@@ -439,6 +444,15 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
                                (cx<T>*)c.ws, c.flags);
         }
         const int mt = mat && !staged ? 1 : 0;
+        if (!mt && rhs && b.K16 == 1) {
+            // y' alone with at most 16 columns: 16 x 16 tiles waste half as
+            // many MFMA columns as 32 x 32 ones
+            const int nt = b.S;
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 1>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, 0, rhs, (const cx<T>*)inA,
+                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+            return;
+        }
         const int nt = (mt ? b.T32 * (b.T32 + 1) / 2 + b.T32 * b.T32 : 0) + (rhs ? b.T32 * b.K32 : 0);
         if (nt > 0)
             hipLaunchKernelGGL((crs::k_reduce_big<T, 2>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,

@@ -290,8 +290,13 @@ __device__ __forceinline__ void wave_lds_sync()
 
 // ------------------------------------------------------------- k_potrf_big
 
-template <class T>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_potrf_big(const Seg* __restrict__ segs, int nseg,
+// RB: the diagonal tile's Cholesky and inverse read the rows of L through
+// the scalar registers (lane c broadcasts row c) and the kernel is held to
+// three waves per SIMD; otherwise the rows go through LDS and the compiler
+// keeps two waves per SIMD.  The first is faster at m <= 64 (the diagonal
+// tiles are a larger share of the work), the second at m = 256.
+template <class T, bool RB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2, 8))) void k_potrf_big(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, const cx<T>* __restrict__ inA,
                                                    cx<T>* __restrict__ W,
                                                    unsigned long long* __restrict__ flags)
@@ -341,10 +346,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         }
         __syncthreads();
         // diagonal tile (wave 0): lane r & 15 keeps row r in registers;
-        // left-looking Cholesky in which lane c broadcasts the finished
-        // entries of row c through the scalar registers; then lane r forms
-        // column r of D = L_II^{-1} by forward substitution, reading the
-        // rows of L the same way
+        // left-looking Cholesky whose later columns read the finished rows
+        // of L by broadcast (scalar registers, or LDS over S_I, already in
+        // registers); then lane r forms column r of D = L_II^{-1} by forward
+        // substitution
         if (wv == 0) {
             const int r = lane & 15, gi = c0 + r;
             const bool real = gi < m;
@@ -364,13 +369,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                 cx<T> s0 = a[c], s1 = czero<T>();
 #pragma unroll
                 for (int u = 0; u + 1 < c; u += 2) {
-                    msub_cb(s0, a[u], lane_bcast(a[u], c));
-                    msub_cb(s1, a[u + 1], lane_bcast(a[u + 1], c));
+                    if constexpr (RB) {
+                        msub_cb(s0, a[u], lane_bcast(a[u], c));
+                        msub_cb(s1, a[u + 1], lane_bcast(a[u + 1], c));
+                    } else {
+                        msub_cb(s0, a[u], sT[c * 17 + u]);
+                        msub_cb(s1, a[u + 1], sT[c * 17 + u + 1]);
+                    }
                 }
                 if (c & 1)
-                    msub_cb(s0, a[c - 1], lane_bcast(a[c - 1], c));
+                    msub_cb(s0, a[c - 1], RB ? lane_bcast(a[c - 1], c) : sT[c * 17 + c - 1]);
                 const cx<T> sv{s0.r + s1.r, s0.i + s1.i};
-                const T dg = lane_bcast(sv.r, c);
+                const T dg = RB ? lane_bcast(sv.r, c) : __shfl(sv.r, c);
                 const T inv = rsqrt_nr(dg);
                 const T sq = dg * inv;
                 fail |= (c0 + c < m) && !(dg > T(0));
@@ -378,6 +388,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                     a[c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
                 else if (r > c)
                     a[c] = cx<T>{sv.r * inv, sv.i * inv};
+                if constexpr (!RB) {
+                    if (lane < 16)
+                        sT[r * 17 + c] = a[c];
+                    wave_lds_sync();
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (lane < 16 && real) {
@@ -392,8 +407,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                 cx<T> v = q == r ? cx<T>{T(1), T(0)} : czero<T>();
 #pragma unroll
                 for (int u = 0; u < q; ++u)
-                    msub(v, lane_bcast(a[u], q), z[u]);
-                const T iq = lane_bcast(a[q].i, q);
+                    msub(v, RB ? lane_bcast(a[u], q) : sT[q * 17 + u], z[u]);
+                const T iq = RB ? lane_bcast(a[q].i, q) : sT[q * 17 + q].i;
                 z[q] = cx<T>{v.r * iq, v.i * iq};
             }
             if (lane < 16) {
