@@ -444,6 +444,15 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
                                (cx<T>*)c.ws, c.flags);
         }
         const int mt = mat && !staged ? 1 : 0;
+        if (mt) {
+            // 32 < m <= 64: one wave per 16 x 16 tile (four times the waves of
+            // the 32 x 32 tiles for these short contractions)
+            const int nt = b.S * (b.S + 1) / 2 + b.S * b.S + (rhs ? b.S * b.K16 : 0);
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 1>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, 1, rhs, (const cx<T>*)inA,
+                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+            return;
+        }
         if (!mt && rhs && b.K16 == 1) {
             // y' alone with at most 16 columns: 16 x 16 tiles waste half as
             // many MFMA columns as 32 x 32 ones

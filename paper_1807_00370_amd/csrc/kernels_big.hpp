@@ -15,7 +15,7 @@
 //                 blocked forward substitution
 //                 X_I = D_I (G_I - L[I][<I] X_{<I}), the Section 4 recipe
 //                 L \ G for the three operands of Eq. (Formulas).
-//   k_reduce_big  one wave per (kept block, 32 x 32 tile) of the reduced
+//   k_reduce_big  one wave per (kept block, 16 or 32 wide tile) of the reduced
 //                 system A' = A_q - P_l^H P_l - Q_r^H Q_r (lower triangle),
 //                 B' = -P_r^H Q_r, y' = y_q - P_l^H g_l - Q_r^H g_r; with
 //                 16 x 16 tiles it also serves the levels of m <= 32 that
@@ -722,8 +722,10 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
 // One wave per output tile of TT = 16 TW rows and columns of a kept block
 // (NT = ceil(m / TT)): with_mat gives the NT (NT + 1) / 2 lower tiles of A'
 // and the NT^2 tiles of B', with_rhs the NT ceil(k / TT) tiles of y' after
-// them.  TW = 2 serves the blocks above 32; TW = 1 the levels of smaller
-// blocks with too few blocks to fill the GPU one wave per block.
+// them.  TW = 2 serves the right-hand sides of blocks above 64 (k > 16);
+// TW = 1 the blocks of 32 < m <= 64, the right-hand sides with k <= 16 of
+// larger blocks, and the levels of m <= 32 with too few blocks to fill the
+// GPU one wave per block.
 template <class T, int TW>
 __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int ntile, int with_mat,
