@@ -138,6 +138,18 @@ int crsolve_workspace_size(const crsolve_plan *plan, size_t *bytes);
 int crsolve_factor(crsolve_plan *plan, const void *A, const void *B, void *ws, size_t ws_bytes,
                    crsolve_info *info, void *stream);
 
+/* Positive-definiteness test (Section 2, "Determination of Positive
+ * Definiteness", and Section 4): the block matrix is HPD if and only if
+ * every Cholesky factorization of the reduction succeeds.  Runs the matrix
+ * part of the levels only (no right-hand side; the levels after a
+ * breakdown skip their work) and writes info[s].status = 0 (HPD) or 1 with
+ * the first failing (level, block).  Same arguments, errors and stream
+ * behaviour as crsolve_factor, whose factors it leaves in ws (a solve may
+ * follow).  With FP32_REFINE the verdict is the FP64 one (an FP32
+ * breakdown is re-checked in FP64).  CR only. */
+int crsolve_check_hpd(crsolve_plan *plan, const void *A, const void *B, void *ws,
+                      size_t ws_bytes, crsolve_info *info, void *stream);
+
 /* Solve with the factors in ws: forward reduction of y through the levels,
  * then recovery of the eliminated unknowns level by level (Section 2, phase
  * 3).  A and B are read only by FP32_REFINE (FP64 residuals); they may be

@@ -20,7 +20,8 @@ SCHED_CR, SCHED_PCR = 0, 1
 
 OK, EINVAL, EHIP, EWORKSPACE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
 
-EXPORTS = ("crsolve_plan_create", "crsolve_workspace_size", "crsolve_factor", "crsolve_solve",
+EXPORTS = ("crsolve_plan_create", "crsolve_workspace_size", "crsolve_factor", "crsolve_check_hpd",
+           "crsolve_solve",
            "crsolve_factor_solve", "crsolve_backward", "crsolve_residual", "crsolve_set_graphs",
            "crsolve_autotune", "crsolve_set_tuning", "crsolve_timing_enable",
            "crsolve_timing_read", "crsolve_plan_destroy", "crsolve_error_string")
@@ -77,6 +78,7 @@ def load():
     lib.crsolve_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(P)]
     lib.crsolve_workspace_size.argtypes = [P, ctypes.POINTER(S)]
     lib.crsolve_factor.argtypes = [P, P, P, P, S, P, P]
+    lib.crsolve_check_hpd.argtypes = [P, P, P, P, S, P, P]
     lib.crsolve_solve.argtypes = [P, P, S, P, P, P, P, P, P]
     lib.crsolve_factor_solve.argtypes = [P, P, P, P, P, S, P, P, P]
     lib.crsolve_backward.argtypes = [P, P, S, P, P, P, P, P, P]
@@ -136,6 +138,10 @@ class Plan:
     def factor(self, A, B, ws, info, stream):
         check("crsolve_factor", load().crsolve_factor(self._h, A, B, ws, self.ws_bytes, info,
                                                       stream))
+
+    def check_hpd(self, A, B, ws, info, stream):
+        check("crsolve_check_hpd", load().crsolve_check_hpd(self._h, A, B, ws, self.ws_bytes, info,
+                                                            stream))
 
     def solve(self, ws, A, B, y, x, info, stream):
         check("crsolve_solve", load().crsolve_solve(self._h, ws, self.ws_bytes, A, B, y, x, info,

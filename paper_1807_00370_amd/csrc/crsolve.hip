@@ -1703,6 +1703,13 @@ int crsolve_factor(crsolve_plan* p, const void* A, const void* B, void* ws, size
     return last_err();
 }
 
+int crsolve_check_hpd(crsolve_plan* p, const void* A, const void* B, void* ws, size_t ws_bytes,
+                      crsolve_info* info, void* stream)
+{
+    // the factorization is the test: its flag is the verdict
+    return crsolve_factor(p, A, B, ws, ws_bytes, info, stream);
+}
+
 int crsolve_solve(const crsolve_plan* p, void* ws, size_t ws_bytes, const void* A, const void* B,
                   const void* y, void* x, crsolve_info* info, void* stream)
 {

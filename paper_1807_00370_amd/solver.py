@@ -92,6 +92,15 @@ class Solver:
         self.plan.factor(_ptr(A), _ptr(B), _ptr(self.ws), _ptr(self.info), _stream(self.device))
         self.factored = True
 
+    def check_hpd(self, A, B) -> np.ndarray:
+        """Positive-definiteness test of every system of the batch (the
+        factorization's breakdown flag; the factors stay usable for solves).
+        Synchronizes; returns one bool per system."""
+        self._mat(A, B)
+        self.plan.check_hpd(_ptr(A), _ptr(B), _ptr(self.ws), _ptr(self.info), _stream(self.device))
+        self.factored = True
+        return self.info_host()["status"] == 0
+
     def solve(self, y, x=None, A=None, B=None):
         """Solve with the stored factors.  The mixed-precision form also needs
         the FP64 matrix (A, B) for its residuals."""
@@ -199,6 +208,21 @@ def solve(A, B, y, schedule="cr"):
     s = Solver([N], [m], [k], dtype=A.dtype, schedule=schedule, device=A.device)
     x = s.factor_solve(A, B, y)
     return x, s.info_host()[0]
+
+
+def check_hpd(A, B):
+    """Is the Hermitian block-tridiagonal matrix (A_1..A_N on the diagonal,
+    B_j at block row j+1, column j) positive definite?  Returns (bool,
+    info_record): the first failing (level, block) when it is not.
+    Synchronizes."""
+    if A.dim() != 3 or A.shape[1] != A.shape[2]:
+        raise ValueError("A must be [N, m, m]")
+    N, m = A.shape[0], A.shape[1]
+    if B.shape != (max(N - 1, 0), m, m):
+        raise ValueError("B must be [N-1, m, m]")
+    s = Solver([N], [m], [1], dtype=A.dtype, device=A.device)
+    ok = s.check_hpd(A.contiguous(), B.contiguous())
+    return bool(ok[0]), s.info_host()[0]
 
 
 class CRSolve(torch.autograd.Function):
