@@ -40,8 +40,11 @@ one the contract names):
                        (and c64 under forms)
   --workload batch     512 ragged systems, N = 2 U{128..--batch-half-max}
   --schedule pcr       Algorithm 1 on the default workload (FP64)
-Profiling runs add --no-autotune (default kernel variants) and --calib-copy
-(a device copy of A of known size for counter calibration).
+Profiling runs add --no-autotune (default kernel variants), --calib-copy
+(a device copy of A of known size for counter calibration) and
+--no-box-peaks.  After the timed steps the roofline entry also reports the
+GPU's achievable peaks measured with library kernels (peak_measured: a 1 GiB
+device copy, 8192^3 FP64 / FP32 GEMMs) and the fraction of those.
 """
 from __future__ import annotations
 
@@ -302,7 +305,63 @@ def kernel_times(torch, sol, step, steps):
     return {kn: (cnt / steps, tot / steps) for kn, (cnt, tot) in kt.items()}
 
 
+_BOX = {}
+
+
+def box_peaks():
+    """Achievable peaks of this GPU, measured with library kernels after the
+    timed region: a 1 GiB device-to-device copy (read + written bytes) for
+    HBM, and 8192^3 FP64 and FP32 GEMMs for the matrix cores.  Context for
+    the published peaks, not a replacement for them."""
+    if _BOX:
+        return _BOX
+    import torch
+    dev = torch.device("cuda:0")
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    _BOX["hbm_GBs"] = 2 * a.numel() * 8 / timed(lambda: b.copy_(a), 10) / 1e9
+    del a, b
+    M = 8192
+    for dt, key in ((torch.float64, "fp64_TFs"), (torch.float32, "fp32_TFs")):
+        g = torch.Generator(device=dev)
+        g.manual_seed(1)
+        x = torch.randn(M, M, dtype=dt, device=dev, generator=g)
+        yv = torch.randn(M, M, dtype=dt, device=dev, generator=g)
+        z = torch.empty_like(x)
+        _BOX[key] = 2.0 * M ** 3 / timed(lambda: torch.matmul(x, yv, out=z), 5) / 1e12
+        del x, yv, z
+    torch.cuda.empty_cache()
+    return _BOX
+
+
+def add_measured_peak(roof):
+    pk = box_peaks()
+    if roof["unit"] == "GB/s":
+        ref = pk["hbm_GBs"]
+    else:
+        ref = pk["fp64_TFs"] if roof["peak"] == PEAK_FP64_TFS else pk["fp32_TFs"]
+    roof["peak_measured"] = ref
+    roof["frac_of_measured"] = roof["achieved"] / ref
+    roof["peak_measured_how"] = ("1 GiB device copy, read + written bytes" if roof["unit"] == "GB/s"
+                                 else "8192^3 GEMM through torch.matmul")
+
+
 def emit(args, value, ms, dtype, config, forms, roof, cpu, model=None):
+    if not args.no_box_peaks and roof is not None:
+        add_measured_peak(roof)
     out = {"metric": METRIC, "value": value, "unit": "block-rows/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
@@ -468,6 +527,8 @@ def main():
                          "Poisson system N=4096, m=256, k=1 with an eigenvector right-hand side")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-box-peaks", action="store_true",
+                    help="skip the measured copy / GEMM peaks reported beside the published ones")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel variants (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -570,6 +631,8 @@ def main():
     else:
         cpu = cpu_baseline(s, args.cpu_budget)
     fb = forms[best]
+    if not args.no_box_peaks:
+        add_measured_peak(fb["roofline"])
     model_ms = max(fb["model_bytes"] / (PEAK_HBM_GBS * 1e9),
                    fb["model_flops"] / (PEAK_FP64_TFS * 1e12)) * 1e3
     out = {
