@@ -72,7 +72,7 @@ __device__ __forceinline__ double wave_sum(double v)
 // rows 16 ti .. 16 ti + 15, stored in R (unless R is null) as FP32 (r_f32)
 // or FP64; with S = ceil(m / 16) tiles per row and it = j S + ti,
 // part[2 (ob0 + it)] = ||rows of r_j||_F^2, part[2 (ob0 + it) + 1] = the
-// same for y_j.
+// same for y_j.  MFMA products, VALU products for k = 1.
 __global__ __launch_bounds__(64) void k_residual(const Seg* __restrict__ segs, int nseg,
                                                  int64_t total, const cx<double>* __restrict__ A,
                                                  const cx<double>* __restrict__ B,
@@ -100,7 +100,54 @@ __global__ __launch_bounds__(64) void k_residual(const Seg* __restrict__ segs, i
     const cx<T>* xj = X + s.ox + j * mk;
     const cx<T>* yj = Y + s.oy + j * mk;
     double sr = 0.0, sy = 0.0;
-    for (int c0 = 0; c0 < k; c0 += 16) {
+    if (k == 1) {
+        // one right-hand side: VALU products (an MFMA tile would use one of
+        // its 16 columns).  Lane (kr, cc) sums the contraction indices
+        // t = kr, kr + 4, ... of row i = r0 + cc with the loads of the MFMA
+        // path (16 rows x 4 consecutive t per load), then the four kr lanes
+        // of a row are combined.
+        const int i = r0 + cc;
+        const bool oi = i < m, hasM = j > 0, hasP = j + 1 < n;
+        cx<T> acc = czero<T>();
+#pragma unroll 4
+        for (int tt = kr; tt < m; tt += 4) {
+            cx<T> hv = czero<T>(), bm = czero<T>(), bp = czero<T>();
+            if (oi) {
+                hv = Aj[tt <= i ? i * m + tt : tt * m + i];
+                hv.i = tt < i ? hv.i : (tt == i ? T(0) : -hv.i);
+                if (hasM)
+                    bm = Bm[i * m + tt];
+                if (hasP) {
+                    bp = Bj[tt * m + i];
+                    bp.i = -bp.i; // (B_j^H)[i][t] = conj(B_j[t][i])
+                }
+            }
+            const cx<T> x0 = xj[tt];
+            const cx<T> xm = hasM ? xj[tt - mk] : czero<T>();
+            const cx<T> xp = hasP ? xj[tt + mk] : czero<T>();
+            acc.r += hv.r * x0.r - hv.i * x0.i + bm.r * xm.r - bm.i * xm.i + bp.r * xp.r -
+                     bp.i * xp.i;
+            acc.i += hv.r * x0.i + hv.i * x0.r + bm.r * xm.i + bm.i * xm.r + bp.r * xp.i +
+                     bp.i * xp.r;
+        }
+        acc.r += __shfl_xor(acc.r, 16);
+        acc.i += __shfl_xor(acc.i, 16);
+        acc.r += __shfl_xor(acc.r, 32);
+        acc.i += __shfl_xor(acc.i, 32);
+        if (kr == 0 && oi) {
+            const cx<T> y = yj[i];
+            const cx<T> r{y.r - acc.r, y.i - acc.i};
+            sr += r.r * r.r + r.i * r.i;
+            sy += y.r * y.r + y.i * y.i;
+            if (R) {
+                if (r_f32)
+                    ((cx<float>*)R)[s.og + j * mk + i] = cx<float>{(float)r.r, (float)r.i};
+                else
+                    ((cx<double>*)R)[s.og + j * mk + i] = r;
+            }
+        }
+    }
+    for (int c0 = 0; c0 < k && k > 1; c0 += 16) {
         const int cw = min(16, k - c0);
         v4 cr[1][1], ci[1][1];
         zero_acc<T, 1, 1>(cr, ci);

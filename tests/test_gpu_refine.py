@@ -146,10 +146,13 @@ def test_refine_ragged_batch(tdev):
 
 
 def test_library_residual_matches_oracle(tdev):
-    """crsolve_residual (FP64 on the device) equals the oracle's residual."""
+    """crsolve_residual (FP64 on the device) equals the oracle's residual:
+    MFMA tiles for k > 4, VALU products for k <= 4, block sizes with a
+    partial last 16-row tile."""
     torch, dev = tdev
     from paper_1807_00370_amd.solver import Solver
-    shapes = [(300, 32, 16), (129, 8, 1), (64, 64, 4)]
+    shapes = [(300, 32, 16), (129, 8, 1), (64, 64, 4), (50, 20, 3), (7, 100, 2), (33, 40, 5),
+              (1, 9, 1)]
     systems = [W.random_hpd(N, m, k, 1300 + i) for i, (N, m, k) in enumerate(shapes)]
     A = np.concatenate([s.A.ravel() for s in systems])
     B = np.concatenate([s.B.ravel() for s in systems])
