@@ -199,10 +199,11 @@ int crsolve_set_graphs(crsolve_plan *plan, int enable);
  * times, on the given data, the two kernel variants of each level role --
  * one-wave/MFMA kernels and work-group kernels -- for the elimination, the
  * reduced-system formation and the back substitution, and keeps the faster
- * one (synchronizes; overwrites x and the workspace).  Blocks above 32 have
+ * one (synchronizes; overwrites x and the workspace).  Blocks of 33..64 have
  * one elimination and one back-substitution kernel (tiled) and two variants
- * of the reduced-system formation (tiled, or one wave per block), so only
- * that role is tuned for them.  The choice is returned as a short text (cap
+ * of the reduced-system formation (16 x 16 tiles, or one wave per block), so
+ * only that role is tuned for them; blocks above 64 have one kernel per role
+ * and are not tuned.  The choice is returned as a short text (cap
  * bytes, NUL-terminated), one token "r<role>c<class>f<fp64>=<variant>;" per
  * tuned role, that crsolve_set_tuning applies to another plan, e.g. from a
  * cache file.  NATIVE plans only. */

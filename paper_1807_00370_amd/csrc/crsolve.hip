@@ -1645,8 +1645,9 @@ int crsolve_autotune(crsolve_plan* p, const void* A, const void* B, const void* 
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < kNumCls; ++c)
             for (int f = 0; f < 2; ++f) {
-                // tiled classes have one elimination and one back-substitution kernel
-                const bool tuned = seen[r][c][f] && !(tiled(c) && r != 1);
+                // tiled classes have one elimination and one back-substitution
+                // kernel, and above 64 one reduced-system form as well
+                const bool tuned = seen[r][c][f] && !(tiled(c) && r != 1) && c != kBig;
                 const int v = (tuned && t[1][r][c][f] < t[0][r][c][f]) ? 1 : 0;
                 p->var[r][c][f] = v;
                 if (tuned)

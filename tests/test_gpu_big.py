@@ -216,3 +216,28 @@ def test_poisson_full_size_closed_form(tdev):
     res_rounded_exact = oracle.rel_residual(s.A, s.B, x_exact, s.y)
     print("residual %.3e, of the rounded exact solution %.3e" % (res, res_rounded_exact))
     assert res <= 16 * u * kappa
+
+
+def test_big_autotune_mixed_classes(tdev):
+    """A plan with blocks of 33..64 and above 64: the tuner reports the
+    reduced-system role of the 33..64 class only (one kernel per role above
+    64), and the tuned plan still matches the oracle."""
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import Solver
+    systems = [W.random_hpd(24, 48, 3, 9910), W.random_hpd(20, 80, 2, 9911)]
+    A = np.concatenate([s.A.ravel() for s in systems])
+    B = np.concatenate([s.B.ravel() for s in systems])
+    y = np.concatenate([s.y.ravel() for s in systems])
+    At, Bt, yt = (torch.from_numpy(v).to(dev) for v in (A, B, y))
+    sol = Solver([s.N for s in systems], [s.m for s in systems], [s.k for s in systems],
+                 device=dev)
+    choice = sol.autotune(At, Bt, yt)
+    toks = [t for t in choice.split(";") if t]
+    assert len(toks) == 1 and toks[0].startswith("r1c4f1="), choice
+    x = sol.factor_solve(At, Bt, yt).cpu().numpy()
+    off = 0
+    for s in systems:
+        xs = x[off:off + s.y.size].reshape(s.y.shape)
+        off += s.y.size
+        xo, _ = oracle.solve_cr(s.A, s.B, s.y)
+        assert _rel(xs, xo) <= TOL64
