@@ -183,9 +183,67 @@ def adjoint_model(N, m, k, s):
     return tot
 
 
-def cpu_baseline(s, budget_s: float, what: str = "full workload", solver: str = "cr"):
+def host_cpu():
+    """CPU model name and logical CPU count of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def banded_lower(A, B):
+    """LAPACK lower band storage of the Hermitian block-tridiagonal matrix
+    (half-bandwidth 2m - 1): ab[i - j, j] = D[i, j] for i >= j."""
+    N, m, _ = A.shape
+    ab = np.zeros((2 * m, N * m), np.complex128)
+    for r in range(m):
+        for q in range(r + 1):
+            v = A[:, r, q]
+            ab[r - q, q::m] = v.real if r == q else v
+        if N > 1:
+            for q in range(m):
+                ab[m + r - q, q:(N - 1) * m:m] = B[:, r, q]
+    return ab
+
+
+def cpu_extras(m, k, seed):
+    """Per-block-row CPU rates on an N=4096 sample of the same block shape:
+    the oracle on one core, and LAPACK's banded Hermitian solver (zpbsv via
+    scipy.linalg.solveh_banded) as a library reference."""
+    import oracle
+    import scipy.linalg
+    from paper_1807_00370_amd import workloads as W
+    smp = W.random_hpd(4096, m, k, seed)
+    nt = oracle.num_threads()
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    oracle.solve_cr(smp.A, smp.B, smp.y)
+    t1 = time.perf_counter()
+    oracle.set_num_threads(nt)
+    ab = banded_lower(smp.A, smp.B)
+    t2 = time.perf_counter()
+    scipy.linalg.solveh_banded(ab, smp.y.reshape(-1, k), lower=True, check_finite=False)
+    t3 = time.perf_counter()
+    return {"value_1core": {"value": smp.N / (t1 - t0), "unit": "block-rows/s", "cores": 1,
+                            "sample": "oracle, N=4096 sample (m=%d, k=%d), one solve in %.2f s"
+                                      % (m, k, t1 - t0)},
+            "lapack_banded": {"value": smp.N / (t3 - t2), "unit": "block-rows/s",
+                              "sample": "scipy.linalg.solveh_banded (LAPACK zpbsv, band "
+                                        "Cholesky, half-bandwidth %d), N=4096 sample, one solve "
+                                        "in %.2f s" % (2 * m - 1, t3 - t2)}}
+
+
+def cpu_baseline(s, budget_s: float, what: str = "full workload", solver: str = "cr",
+                 extras=True):
     """The oracle's one-sided reduction (or Algorithm 1) on the host cores (at
-    least one solve, repeated until the budget is spent)."""
+    least one solve, repeated until the budget is spent); also returns the
+    oracle's x of the last solve."""
     import oracle
     oracle.build(force=False)
     fn = oracle.solve_pcr if solver == "pcr" else oracle.solve_cr
@@ -197,24 +255,19 @@ def cpu_baseline(s, budget_s: float, what: str = "full workload", solver: str = 
         if el >= budget_s or reps >= 8:
             break
     assert info["status"] == 0
-    return {"value": s.N * reps / el, "unit": "block-rows/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%s (N=%d, m=%d, k=%d, complex128), FP64 %s, %d solve(s) in %.1f s" % (
-                what, s.N, s.m, s.k, "Algorithm 1" if solver == "pcr" else
-                "one-sided cyclic reduction", reps, el)}
+    out = {"value": s.N * reps / el, "unit": "block-rows/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": "%s (N=%d, m=%d, k=%d, complex128), FP64 %s, %d solve(s) in %.1f s" % (
+               what, s.N, s.m, s.k, "Algorithm 1" if solver == "pcr" else
+               "one-sided cyclic reduction", reps, el)}
+    out.update(host_cpu())
+    if extras:
+        out.update(cpu_extras(s.m, s.k, 180700370 + 97))
+    return out, x
 
 
 def timed_steps(torch, sol, A, B, y, x, steps, warmup):
-    for _ in range(warmup):
-        sol.factor_solve(A, B, y, x)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(steps):
-        sol.factor_solve(A, B, y, x)
-    ev1.record()
-    torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / steps
+    return time_steps(torch, lambda: sol.factor_solve(A, B, y, x), steps, warmup)
 
 
 def time_form(torch, sol, A, B, y, x, steps, warmup):
@@ -222,6 +275,7 @@ def time_form(torch, sol, A, B, y, x, steps, warmup):
     step time, and per-kernel event timings of eager steps."""
     sol.set_graphs(True)
     ms = timed_steps(torch, sol, A, B, y, x, steps, warmup)
+    _STEP_STATS["graph_mean"] = _STEP_STATS["mean"]
     sol.set_graphs(False)
     ms_eager = timed_steps(torch, sol, A, B, y, x, steps, 1)
     # per-kernel durations from HIP events bracketing each launch
@@ -282,17 +336,25 @@ def roofline(per_step, mod, prec_f64, form="fp64", shape=(65536, 32, 16)):
     return r
 
 
+_STEP_STATS = {}
+
+
 def time_steps(torch, step, steps, warmup):
+    """Median step time (ms) over `steps` steps, each bracketed by HIP events on
+    the current stream; the mean over the same steps is kept in _STEP_STATS."""
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
         step()
-    ev1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / steps
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    _STEP_STATS["mean"] = ev[0].elapsed_time(ev[-1]) / steps
+    _STEP_STATS["min"] = min(per)
+    return float(np.median(per))
 
 
 def kernel_times(torch, sol, step, steps):
@@ -435,21 +497,49 @@ def run_batch(args, torch, W, dev):
     """Batching workload: 512 independent systems of uneven N, m, k in one
     plan (one launch per level, block-size class and precision), the launch
     sequence replayed as a HIP graph; complex128 inputs solved by the
-    FP32 + FP64-refinement form (the stated form) and by the FP64 form."""
+    FP32 + FP64-refinement form (the stated form) and, when its workspace
+    fits beside the inputs, by the FP64 form."""
     import oracle
+    from paper_1807_00370_amd import _lib
     from paper_1807_00370_amd.solver import Solver
     t0 = time.perf_counter()
     shapes = W.batch_shapes(W.BATCH_COUNT, W.config_seed(3), n_half_range=(128, args.batch_half_max))
-    # forked generator processes (no GPU use before this point), one per core up to 16
-    hA, hB, hy = W.batch_packed(shapes, W.config_seed(3), workers=min(16, os.cpu_count() or 1))
-    print("batch inputs generated in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    # generator processes forked before this process touches the GPU
+    stream = W.BatchStream(shapes, W.config_seed(3), workers=min(16, os.cpu_count() or 1))
     Ns, ms_, ks = [q[0] for q in shapes], [q[1] for q in shapes], [q[2] for q in shapes]
-    A, B, y = (torch.from_numpy(v).to(dev) for v in (hA, hB, hy))
-    del hA, hB, hy
-    x = torch.empty_like(y)
     rows = sum(Ns)
+    nA, nB, ny = stream.offA[-1], stream.offB[-1], stream.offy[-1]
+    A = torch.empty(nA, dtype=torch.complex128, device=dev)
+    B = torch.empty(max(nB, 1), dtype=torch.complex128, device=dev)[:nB]
+    y = torch.empty(ny, dtype=torch.complex128, device=dev)
+    done = 0
+    for i, a_, b_, y_ in stream:
+        A[stream.offA[i]:stream.offA[i + 1]].copy_(torch.from_numpy(a_.ravel()))
+        B[stream.offB[i]:stream.offB[i + 1]].copy_(torch.from_numpy(b_.ravel()))
+        y[stream.offy[i]:stream.offy[i + 1]].copy_(torch.from_numpy(y_.ravel()))
+        done += 1
+        if done % 64 == 0:
+            print("batch inputs: %d of %d systems on the GPU (%.0f s)" % (
+                done, len(shapes), time.perf_counter() - t0), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    print("batch inputs generated in %.1f s: %d block rows, %.1f GB" % (
+        time.perf_counter() - t0, rows, (nA + nB + ny) * 16 / 1e9), file=sys.stderr, flush=True)
+    x = torch.empty_like(y)
+    # oracle reference for the first 16 systems (error against FP64 per result)
+    ref = W.batch_systems(shapes[:16], W.config_seed(3))
+    xo_ref = [oracle.solve_cr(q.A, q.B, q.y)[0] for q in ref]
     forms = {}
     for form in ("fp32_refine", "fp64"):
+        prec = _lib.PREC_FP32_REFINE if form != "fp64" else _lib.PREC_NATIVE
+        ws = _lib.Plan(Ns, ms_, ks, precision=prec).ws_bytes
+        free, _ = torch.cuda.mem_get_info(dev)
+        if ws + (2 << 30) > free:
+            forms[form] = {"skipped": "workspace of %.1f GB exceeds the %.1f GB of device memory "
+                                      "left beside the %.1f GB of inputs and x" % (
+                                          ws / 1e9, free / 1e9, (nA + nB + 2 * ny) * 16 / 1e9),
+                           "workspace_bytes": ws}
+            print("batch %s: %s" % (form, forms[form]["skipped"]), file=sys.stderr, flush=True)
+            continue
         if form == "fp64":
             sol = Solver(Ns, ms_, ks, device=dev)
             tuning = sol.autotune(A, B, y)
@@ -460,26 +550,32 @@ def run_batch(args, torch, W, dev):
         sol.set_graphs(True)
         step = lambda: sol.factor_solve(A, B, y, x)
         ms = time_steps(torch, step, args.steps, args.warmup)
+        mean = _STEP_STATS["mean"]
         sol.set_graphs(False)
         per_step = kernel_times(torch, sol, step, args.steps)
         info = sol.info_host()
         if (info["status"] != 0).any():
             raise SystemExit("batch %s: a factorization failed" % form)
         rel = sol.residual(A, B, x, y)
+        xh = x[:stream.offy[16]].cpu().numpy()
+        err = max(float(np.max(np.abs(xh[stream.offy[i]:stream.offy[i + 1]].reshape(q.y.shape) - xo))
+                        / np.max(np.abs(xo))) for i, (q, xo) in enumerate(zip(ref, xo_ref)))
         mod = {}
         for i, (N, m, k) in enumerate(zip(Ns, ms_, ks)):
             add(mod, step_model(form, N, m, k, int(info["refine_iters"][i]) if form != "fp64" else 0))
-        forms[form] = {"ms_per_step": ms, "value": rows / (ms * 1e-3), "tuning": tuning,
+        forms[form] = {"ms_per_step": ms, "ms_per_step_mean": mean, "value": rows / (ms * 1e-3),
+                       "tuning": tuning, "workspace_bytes": ws,
                        "max_rel_residual": float(np.max(rel)),
                        "certified": bool(np.max(rel) <= RTOL),
                        "max_refine_iters": int(np.max(info["refine_iters"])),
                        "fp64_fallbacks": int(np.sum(info["fp64_fallback"])),
+                       "err_vs_oracle_first16": err,
                        "kernel_ms_per_step": {kn: round(v[1], 4) for kn, v in per_step.items()},
                        "roofline": roofline(per_step, mod, form == "fp64", "batch_" + form),
                        "model_bytes": sum(v[0] for v in mod.values()),
                        "model_flops": sum(v[1] for v in mod.values())}
-        print("batch %s: %.3f ms/step, max rel residual %.2e, %s" % (
-            form, ms, np.max(rel), json.dumps(forms[form]["kernel_ms_per_step"])),
+        print("batch %s: %.3f ms/step, max rel residual %.2e, err %.2e, %s" % (
+            form, ms, np.max(rel), err, json.dumps(forms[form]["kernel_ms_per_step"])),
             file=sys.stderr, flush=True)
         del sol
         torch.cuda.synchronize()
@@ -487,7 +583,7 @@ def run_batch(args, torch, W, dev):
     if not args.no_cpu_baseline:
         oracle.build(force=False)
         reps, done, t0 = 0, 0, time.perf_counter()
-        for q in W.batch_systems(shapes[:16], W.config_seed(3)):
+        for q in ref:
             oracle.solve_cr(q.A, q.B, q.y)
             done += q.N
             reps += 1
@@ -497,7 +593,8 @@ def run_batch(args, torch, W, dev):
         cpu = {"value": done / el, "unit": "block-rows/s", "cores": oracle.num_threads(),
                "kind": "oracle", "sample": "the first %d systems of the batch (%d block rows), "
                "FP64 one-sided cyclic reduction, in %.1f s" % (reps, done, el)}
-    best = min((f for f in forms if forms[f]["certified"]), key=lambda f: forms[f]["ms_per_step"])
+        cpu.update(host_cpu())
+    best = min((f for f in forms if forms[f].get("certified")), key=lambda f: forms[f]["ms_per_step"])
     f = forms[best]
     emit(args, f["value"], f["ms_per_step"], "c64+f64" if best != "fp64" else "c128",
          {"workload": "batch of %d independent HPD systems, N = 2 U{128..%d}, m in {8,16,32,64}, "
@@ -519,14 +616,16 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32_refine")
     ap.add_argument("--schedule", choices=("cr", "pcr"), default="cr",
                     help="cr: one-sided reduction (default); pcr: Algorithm 1 as printed (fp64)")
-    ap.add_argument("--batch-half-max", type=int, default=512,
-                    help="batch workload: N = 2 U{128..this}; the stated workload has 4096, whose "
-                         "inputs (~94 GB) and FP64 fallback workspace exceed one GPU's HBM")
+    ap.add_argument("--batch-half-max", type=int, default=4096,
+                    help="batch workload: N = 2 U{128..this} (the stated range is 4096)")
     ap.add_argument("--workload", choices=("random", "poisson", "diff", "batch"), default="random",
                     help="random: the HPD generator at --N/--m/--k; poisson: the block 2D "
                          "Poisson system N=4096, m=256, k=1 with an eigenvector right-hand side")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kappa", action="store_true",
+                    help="skip the calibrated kappa = 1e5 / 1e6 instances of the precision "
+                         "workload (default run only)")
     ap.add_argument("--no-box-peaks", action="store_true",
                     help="skip the measured copy / GEMM peaks reported beside the published ones")
     ap.add_argument("--no-autotune", action="store_true",
@@ -574,10 +673,10 @@ def main():
         del dst
 
     forms = {}
+    xs = {}
     pcr = args.schedule == "pcr"
-    for form in args.forms.split(","):
-        if pcr and form != "fp64":
-            continue  # Algorithm 1 runs in FP64 only
+
+    def run_form(form, s, A, B, y, x, rtol, steps, warmup, tag):
         if form == "fp64":
             sol = Solver([s.N], [s.m], [s.k], dtype=torch.complex128, device=dev,
                          schedule=args.schedule)
@@ -586,15 +685,17 @@ def main():
                          device=dev, rtol=rtol, max_refine=30, fp64_tail_blocks=TAIL)
         tuning = (sol.autotune(A, B, y) if form == "fp64" and s.m <= 64 and not pcr
                   and not args.no_autotune else None)
-        ms, ms_eager, per_step = time_form(torch, sol, A, B, y, x, args.steps, args.warmup)
+        ms, ms_eager, per_step = time_form(torch, sol, A, B, y, x, steps, warmup)
+        mean = _STEP_STATS["graph_mean"]
         info = sol.info_host()[0]
         if info["status"] != 0:
-            raise SystemExit("%s: factorization failed: %s" % (form, info))
+            raise SystemExit("%s: factorization failed: %s" % (tag, info))
         rel = sol.residual(A, B, x, y)[0]
         iters = int(info["refine_iters"]) if form != "fp64" else 0
         mod = pcr_model(s.N, s.m, s.k) if pcr else step_model(form, s.N, s.m, s.k, iters)
-        forms[form] = {
+        rec = {
             "ms_per_step": ms,
+            "ms_per_step_mean": mean,
             "ms_per_step_eager": ms_eager,
             "tuning": tuning,
             "value": s.N / (ms * 1e-3),
@@ -602,6 +703,7 @@ def main():
             "certified": bool(rel <= rtol),
             "refine_iters": iters,
             "fp64_fallback": int(info["fp64_fallback"]) if form != "fp64" else 0,
+            "workspace_bytes": sol.plan.ws_bytes,
             "kernel_ms_per_step": {kn: round(v[1], 4) for kn, v in per_step.items()},
             "kernel_launches_per_step": {kn: v[0] for kn, v in per_step.items()},
             "roofline": roofline(per_step, mod, form == "fp64", ("pcr_" if pcr else "") + form,
@@ -609,27 +711,83 @@ def main():
             "model_bytes": sum(v[0] for v in mod.values()),
             "model_flops": sum(v[1] for v in mod.values()),
         }
-        print("%s: %.3f ms/step, rel residual %.2e, %s" % (form, ms, rel, json.dumps(
-            forms[form]["kernel_ms_per_step"])), file=sys.stderr, flush=True)
+        print("%s: %.3f ms/step, rel residual %.2e, %s" % (tag, ms, rel, json.dumps(
+            rec["kernel_ms_per_step"])), file=sys.stderr, flush=True)
+        xh = x.cpu().numpy()
         del sol
         torch.cuda.synchronize()
+        return rec, xh
+
+    for form in args.forms.split(","):
+        if pcr and form != "fp64":
+            continue  # Algorithm 1 runs in FP64 only
+        forms[form], xs[form] = run_form(form, s, A, B, y, x, rtol, args.steps, args.warmup, form)
 
     certified = [f for f in forms if forms[f]["certified"]]
     if not certified:
         raise SystemExit("no form reached the residual bound: %s" % json.dumps(forms))
     best = min(certified, key=lambda f: forms[f]["ms_per_step"])
+    xo = None
     if args.no_cpu_baseline:
         cpu = None
     elif args.workload == "poisson":
         # bounded sample: the same Poisson blocks with N = 256 (per block row the
         # reduction costs about the same at any N)
-        cpu = cpu_baseline(W.poisson(256, W.POISSON["m"]), args.cpu_budget,
-                           "sample of the Poisson workload")
+        cpu, _ = cpu_baseline(W.poisson(256, W.POISSON["m"]), args.cpu_budget,
+                              "sample of the Poisson workload", extras=False)
     elif pcr:
-        cpu = cpu_baseline(W.random_hpd(4096, s.m, s.k, W.config_seed(1, 1)), args.cpu_budget,
-                           "N=4096 sample of the workload, Algorithm 1", solver="pcr")
+        cpu, _ = cpu_baseline(W.random_hpd(4096, s.m, s.k, W.config_seed(1, 1)), args.cpu_budget,
+                              "N=4096 sample of the workload, Algorithm 1", solver="pcr",
+                              extras=False)
     else:
-        cpu = cpu_baseline(s, args.cpu_budget)
+        cpu, xo = cpu_baseline(s, args.cpu_budget)
+    # error of every form against the FP64 oracle (the closed form for Poisson)
+    if args.workload == "poisson":
+        xref = s.y / s.meta["lam"]
+        for f in forms:
+            forms[f]["err_vs_exact"] = float(np.max(np.abs(xs[f] - xref)) / np.max(np.abs(xref)))
+    else:
+        if xo is None and not args.no_cpu_baseline:
+            import oracle
+            xo, _ = oracle.solve_cr(s.A, s.B, s.y)
+        if xo is not None:
+            for f in forms:
+                forms[f]["err_vs_oracle"] = float(np.max(np.abs(xs[f] - xo)) / np.max(np.abs(xo)))
+    del xs
+
+    # the precision workload at calibrated condition numbers (shifts from the
+    # oracle-only calibration in tests/golden/kappa_shifts.json)
+    if (args.workload == "random" and not pcr and not args.no_kappa
+            and (s.N, s.m, s.k) == (W.LARGE["N"], W.LARGE["m"], W.LARGE["k"])):
+        import oracle
+        with open(os.path.join(ROOT, "tests", "golden", "kappa_shifts.json")) as fh:
+            shifts = json.load(fh)["shifts"]
+        del A, B, y
+        t0 = time.perf_counter()
+        base = W.random_hpd(**W.LARGE, seed=W.config_seed(2))
+        print("precision workload generated in %.1f s" % (time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+        A0 = torch.from_numpy(base.A).to(dev)
+        B = torch.from_numpy(base.B).to(dev)
+        y = torch.from_numpy(base.y).to(dev)
+        idx = np.arange(base.m)
+        for kap, c in sorted(shifts.items(), key=lambda kv: float(kv[0])):
+            A = A0.clone()
+            A.diagonal(dim1=1, dim2=2).sub_(c)
+            sk = W.System(base.A.copy(), base.B, base.y)
+            sk.A[:, idx, idx] -= c
+            xo_k, io_k = oracle.solve_cr(sk.A, sk.B, sk.y)
+            assert io_k["status"] == 0
+            for form in args.forms.split(","):
+                tag = "%s_kappa%s" % (form, kap)
+                rec, xh = run_form(form, sk, A, B, y, x, rtol, min(args.steps, 5), 2, tag)
+                rec["kappa"] = float(kap)
+                rec["diag_shift"] = c
+                rec["err_vs_oracle"] = float(np.max(np.abs(xh - xo_k)) / np.max(np.abs(xo_k)))
+                forms[tag] = rec
+            del A, sk
+        del A0
+
     fb = forms[best]
     if not args.no_box_peaks:
         add_measured_peak(fb["roofline"])
@@ -655,7 +813,8 @@ def main():
                                    "one HPD block-tridiagonal system", s.N, s.m, s.k, rtol,
                                    "Algorithm 1 in place" if pcr else
                                    "one-sided block cyclic reduction", best),
-                   "schedule": args.schedule, "N": s.N, "m": s.m, "k": s.k, "form": best, "rtol": rtol},
+                   "schedule": args.schedule, "N": s.N, "m": s.m, "k": s.k, "form": best, "rtol": rtol,
+                   "timing": "median of %d steps (HIP events per step), graph replay" % args.steps},
         "step_model": {"bytes": fb["model_bytes"], "flops": fb["model_flops"],
                        "roofline_ms": model_ms, "frac_of_step_roofline": model_ms / fb["ms_per_step"]},
         "roofline": fb["roofline"],

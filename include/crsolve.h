@@ -47,9 +47,17 @@
  *                         pointer, unknown enum value)
  *   CRSOLVE_EHIP          a HIP runtime call failed
  *   CRSOLVE_EWORKSPACE    workspace smaller than crsolve_workspace_size
- *   CRSOLVE_EUNSUPPORTED  combination not provided (e.g. PCR with C64 or with
- *                         FP32_REFINE, m > 64)
- *   CRSOLVE_ESTATE        call out of order (solve before factor)
+ *   CRSOLVE_EUNSUPPORTED  combination not provided (PCR with C64 or with
+ *                         FP32_REFINE; m > 256; N > 2^24 with m > 64;
+ *                         N >= 2^30)
+ *   CRSOLVE_ESTATE        call out of order: crsolve_solve or
+ *                         crsolve_backward on a workspace that this plan
+ *                         has not factored (the plan keeps a host record of
+ *                         the workspace pointers passed to a successful
+ *                         crsolve_factor, crsolve_check_hpd, one-sided
+ *                         crsolve_factor_solve or crsolve_autotune; it
+ *                         cannot see a workspace overwritten or reallocated
+ *                         at the same address in between)
  * Numerical status (not positive definite) is data in crsolve_info; the
  * solution of a failed system is NaN.
  */
@@ -68,9 +76,12 @@ typedef enum { CRSOLVE_C128 = 0, CRSOLVE_C64 = 1 } crsolve_dtype;
 /* NATIVE: every level in the dtype.  FP32_REFINE (C128 inputs only): the
  * reduction runs in complex FP32 except for levels with at most
  * fp64_tail_blocks blocks, which run in FP64; the solution is then refined
- * with FP64 residuals r = y - A x until ||r||_F / ||y||_F <= rtol or
- * max_refine corrections; a breakdown in FP32 falls back to an FP64
- * factorization (crsolve_info.fp64_fallback = 1). */
+ * with FP64 residuals r = y - A x until ||r||_F / ||y||_F <= rtol.  A
+ * system falls back to an FP64 factorization and solve of its own
+ * (crsolve_info.fp64_fallback = 1) when its FP32 factorization breaks down,
+ * when its residual fails to decrease from one correction to the next, or
+ * when it still misses rtol after max_refine corrections.  The fallback runs
+ * one system at a time in a workspace region sized for the largest system. */
 typedef enum { CRSOLVE_PREC_NATIVE = 0, CRSOLVE_PREC_FP32_REFINE = 1 } crsolve_precision;
 
 /* CR: one-sided reduction.  At each level the odd-position blocks are
@@ -94,7 +105,8 @@ enum {
 
 typedef struct {
     int32_t batch;            /* number of independent systems, >= 1        */
-    const int32_t *N, *m, *k; /* host arrays [batch]: N >= 1, 1 <= m <= 64,
+    const int32_t *N, *m, *k; /* host arrays [batch]: 1 <= N < 2^30
+                                 (N <= 2^24 when m > 64), 1 <= m <= 256,
                                  k >= 1                                     */
     crsolve_dtype dtype;
     crsolve_precision precision;
@@ -113,9 +125,11 @@ typedef struct {
                              minimum over (level, block)), -1 if none       */
     int64_t block;        /* 1-based index, in the original numbering, of
                              the block row whose pivot broke down, -1       */
-    int32_t refine_iters; /* FP32_REFINE: corrections applied               */
-    int32_t fp64_fallback;/* FP32_REFINE: 1 if FP32 broke down and the
-                             factorization was redone in FP64               */
+    int32_t refine_iters; /* FP32_REFINE: corrections applied to the
+                             returned x (0 for a system that fell back)     */
+    int32_t fp64_fallback;/* FP32_REFINE: 1 if the system was factored and
+                             solved in FP64 (FP32 breakdown, stalled or
+                             unconverged refinement)                        */
     double rel_residual;  /* FP32_REFINE: final ||y - A x||_F / ||y||_F     */
 } crsolve_info;
 
@@ -126,7 +140,9 @@ typedef struct crsolve_plan crsolve_plan;
 int crsolve_plan_create(const crsolve_desc *desc, crsolve_plan **out);
 
 /* Bytes of device workspace the plan needs (factors of every level, the
- * reduced systems, right-hand-side temporaries and the level tables). */
+ * reduced systems, right-hand-side temporaries and the level tables; for
+ * FP32_REFINE also the FP64 residual and correction buffers and the FP64
+ * fallback region of the largest system).  Host only. */
 int crsolve_workspace_size(const crsolve_plan *plan, size_t *bytes);
 
 /* Factor: run the matrix part of every reduction level (Section 2, phase 1
@@ -145,19 +161,25 @@ int crsolve_factor(crsolve_plan *plan, const void *A, const void *B, void *ws, s
  * breakdown skip their work) and writes info[s].status = 0 (HPD) or 1 with
  * the first failing (level, block).  Same arguments, errors and stream
  * behaviour as crsolve_factor, whose factors it leaves in ws (a solve may
- * follow).  With FP32_REFINE the verdict is the FP64 one (an FP32
- * breakdown is re-checked in FP64).  CR only. */
+ * follow).  With FP32_REFINE the verdict of every system is the FP64 one:
+ * after the FP32 factorization each system is factored again by its FP64
+ * plan (one system at a time; the call synchronizes once per system), its
+ * record is the FP64 record, and a system that fails in either precision is
+ * marked in ws for the FP64 path of later solves.  CR only. */
 int crsolve_check_hpd(crsolve_plan *plan, const void *A, const void *B, void *ws,
                       size_t ws_bytes, crsolve_info *info, void *stream);
 
 /* Solve with the factors in ws: forward reduction of y through the levels,
  * then recovery of the eliminated unknowns level by level (Section 2, phase
  * 3).  A and B are read only by FP32_REFINE (FP64 residuals); they may be
- * NULL otherwise.  Systems whose factorization failed get NaN in x.
+ * NULL otherwise.  info (may be NULL) receives the factorization's record
+ * of every system: a system whose factorization failed gets status 1 and
+ * NaN in x.  CRSOLVE_ESTATE if this plan has not factored ws.
  * The solve uses a scratch region of ws that the factors do not occupy, so
  * two solves on the same ws must not overlap in time.  With
  * FP32_REFINE the call synchronizes the stream once per correction to test
- * convergence and writes refine_iters and rel_residual.  CR only. */
+ * convergence, runs the FP64 fallback of the systems that need it, and
+ * writes refine_iters, fp64_fallback and rel_residual.  CR only. */
 int crsolve_solve(const crsolve_plan *plan, void *ws, size_t ws_bytes, const void *A,
                   const void *B, const void *y, void *x, crsolve_info *info, void *stream);
 
@@ -173,7 +195,8 @@ int crsolve_factor_solve(crsolve_plan *plan, const void *A, const void *B, const
  *   grad_y = lam,  grad_A_j = -lam_j x_j^H,
  *   grad_B_j = -(lam_{j+1} x_j^H + x_{j+1} lam_j^H).
  * x must be the solution computed with these factors.  grad_y may alias
- * nothing else.  CR and NATIVE only. */
+ * nothing else.  A failed factorization gives NaN gradients.
+ * CRSOLVE_ESTATE if this plan has not factored ws.  CR and NATIVE only. */
 int crsolve_backward(const crsolve_plan *plan, void *ws, size_t ws_bytes, const void *x,
                      const void *grad_x, void *grad_y, void *grad_A, void *grad_B, void *stream);
 

@@ -60,6 +60,8 @@ def _load():
         lib.cro_backward.restype = None
         lib.cro_num_threads.argtypes = []
         lib.cro_num_threads.restype = ctypes.c_int
+        lib.cro_set_num_threads.argtypes = [ctypes.c_int]
+        lib.cro_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -150,3 +152,8 @@ def backward(x, lam, B_shape=None):
 
 def num_threads() -> int:
     return int(_load().cro_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel regions (CPU-baseline timing)."""
+    _load().cro_set_num_threads(int(n))

@@ -661,3 +661,14 @@ int cro_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the later parallel regions (timing of the CPU baseline). */
+void cro_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}

@@ -11,8 +11,9 @@
 // The mixed-precision form adds conversion jobs (level-0 inputs to FP32, the
 // reduced system back to FP64 at the first FP64 level, the FP64 tail's
 // unknowns into the FP32 correction), the FP64 residual of Eq. (Axb) and a
-// host-driven refinement loop; a breakdown of the FP32 factorization falls
-// back to a complete FP64 plan that shares the workspace.
+// host-driven refinement loop.  A system whose FP32 factorization breaks down,
+// or whose refinement stalls or misses the tolerance, is solved again by a
+// one-system FP64 plan in a workspace region sized for the largest system.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -137,7 +138,8 @@ struct crsolve_plan {
     // workspace layout (bytes)
     size_t off_flags = 0, off_segs = 0, off_jobs = 0, ws_bytes = 0;
     size_t off_part = 0, off_norms = 0, off_info = 0, off_fb = 0;
-    size_t off_d32 = 0; // refinement correction (complex FP32, like y)
+    size_t off_d32 = 0;   // refinement correction (complex FP32, like y)
+    size_t off_fbits = 0; // refinement: int32 per system, 1 = solved by its FP64 plan
 
     std::vector<std::vector<LevelSpec>> lv; // per system
     std::vector<int> sw;                    // first FP64 level per system (refine)
@@ -149,8 +151,22 @@ struct crsolve_plan {
     std::vector<std::vector<CvtLaunch>> cvt_factor_sw, cvt_solve_sw, scatter_sw;
     int nlevels = 0;
 
-    std::unique_ptr<crsolve_plan> fb; // FP64 plan used after an FP32 breakdown
-    mutable bool use_fb = false;
+    // refinement: one FP64 plan per system, run in the region at off_fb
+    // (sized for the largest system) for the systems that fall back
+    std::vector<std::unique_ptr<crsolve_plan>> fbs;
+
+    // workspaces this plan has factored (host record; solve and backward on
+    // any other workspace return CRSOLVE_ESTATE)
+    mutable std::vector<const void*> factored;
+    void mark_factored(const void* ws) const
+    {
+        if (std::find(factored.begin(), factored.end(), ws) == factored.end())
+            factored.push_back(ws);
+    }
+    bool is_factored(const void* ws) const
+    {
+        return std::find(factored.begin(), factored.end(), ws) != factored.end();
+    }
 
     // kernel variant per (role: elim, reduce, back; class; precision):
     // 0 = one-wave / MFMA kernels, 1 = work-group kernels (autotuner)
@@ -690,6 +706,8 @@ int build_plan(crsolve_plan* p)
         a.off = align_up(a.off + (size_t)p->toty * e32);
         p->off_info = a.off;
         a.off = align_up(a.off + sizeof(double) * 2 * p->batch);
+        p->off_fbits = a.off;
+        a.off = align_up(a.off + sizeof(int32_t) * p->batch);
     }
 
     int maxlev = 0;
@@ -952,8 +970,11 @@ int build_plan(crsolve_plan* p)
     p->off_jobs = a.off;
     a.off = align_up(a.off + sizeof(CvtJob) * std::max<size_t>(p->jobs.size(), 1));
     if (refine) {
+        size_t big = 0;
+        for (const auto& q : p->fbs)
+            big = std::max(big, q->ws_bytes);
         p->off_fb = a.off;
-        a.off = align_up(a.off + p->fb->ws_bytes);
+        a.off = align_up(a.off + big);
     }
     p->ws_bytes = a.off;
     return CRSOLVE_OK;
@@ -1213,60 +1234,149 @@ void enqueue_refine_fused(const Ctx& c, const void* A, const void* B, const void
     residual(c, A, B, x, y, true);
 }
 
-// Refinement after a first pass whose residual norms are in the workspace:
-// d = A^{-1} r with the mixed factors and x += d until every system meets
-// rtol (or max_refine passes); writes refine_iters and rel_residual.
-template <class Pass>
-int refine_iterate(const crsolve_plan* p, const Ctx& c, Pass pass, crsolve_info* info)
+// Relative residual of system s from the norm pairs read back by read_norms.
+double rel_of(const std::vector<double>& nh, int s)
 {
-    std::vector<double> nh, tab(2 * p->batch, 0.0);
+    return nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
+}
+
+// Refinement after a first pass whose residual norms are in the workspace:
+// d = A^{-1} r with the mixed factors and x += d while some active system
+// misses rtol.  A system leaves the loop for the FP64 fallback (fb[s] = 1)
+// when its residual fails to decrease from one pass to the next (stalled,
+// diverging or NaN) or when it still misses rtol after max_refine passes.
+// tab receives {corrections applied, relative residual} per system.
+template <class Pass>
+int refine_iterate(const crsolve_plan* p, const Ctx& c, Pass pass, std::vector<char>& fb,
+                   std::vector<double>& tab)
+{
+    std::vector<double> nh, prev(p->batch, 0.0);
+    tab.assign(2 * p->batch, 0.0);
     int it = 0, rc;
     for (;;) {
         if ((rc = read_norms(c, nh)))
             return rc;
         bool done = true;
         for (int s = 0; s < p->batch; ++s) {
-            const double rel = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
+            if (fb[s])
+                continue;
+            const double rel = rel_of(nh, s);
             tab[2 * s] = it;
             tab[2 * s + 1] = rel;
-            if (!(rel <= p->rtol))
-                done = false;
+            if (rel <= p->rtol)
+                continue;
+            if (it > 0 && !(rel < prev[s])) {
+                fb[s] = 1; // no progress: FP32 cannot refine this system
+                continue;
+            }
+            prev[s] = rel;
+            done = false;
         }
-        if (done || it >= p->max_refine)
+        if (done)
             break;
+        if (it >= p->max_refine) {
+            for (int s = 0; s < p->batch; ++s)
+                if (!fb[s] && !(tab[2 * s + 1] <= p->rtol))
+                    fb[s] = 1;
+            break;
+        }
         if ((rc = pass(false)))
             return rc;
         ++it;
     }
-    return write_refine_info(c, info, tab);
+    return CRSOLVE_OK;
 }
 
-// FP64 fallback after a breakdown of the mixed factorization: factor and
-// solve with the FP64 plan, then the residual for the record.
-int fallback_fs(const crsolve_plan* p, const Ctx& c, const void* A, const void* B, const void* y,
-                void* x, crsolve_info* info)
+// The one-system FP64 plan of system s in the fallback region: factor
+// (y == nullptr) or factor and solve, then that system's info record
+// (fp64_fallback = fbflag).
+void fallback_sys(const crsolve_plan* p, char* ws, hipStream_t st, int s, const void* A,
+                  const void* B, const void* y, void* x, crsolve_info* info, int fbflag)
 {
-    const crsolve_plan* q = p->fb.get();
-    Ctx cf = make_ctx(q, c.ws + p->off_fb, c.st);
-    int rc = upload(q, cf.ws, c.st);
-    if (rc)
-        return rc;
+    const crsolve_plan* q = p->fbs[s].get();
+    Ctx cf = make_ctx(q, ws + p->off_fb, st);
+    (void)upload(q, cf.ws, st);
+    const size_t e = sizeof(cx<double>);
+    const char* As = (const char*)A + (size_t)p->offA[s] * e;
+    const char* Bs = (const char*)B + (size_t)p->offB[s] * e;
     init_flags(cf);
-    levels_down(cf, A, B, y, 1, 1);
-    levels_up(cf, x);
-    finalize(cf, info, 1);
-    residual(c, A, B, x, y, false);
-    std::vector<double> nh, tab(2 * p->batch, 0.0);
-    if ((rc = read_norms(c, nh)))
-        return rc;
+    if (y) {
+        levels_down(cf, As, Bs, (const char*)y + (size_t)p->offy[s] * e, 1, 1);
+        levels_up(cf, (char*)x + (size_t)p->offy[s] * e);
+    } else {
+        levels_down(cf, As, Bs, nullptr, 1, 0);
+    }
+    finalize(cf, info ? info + s : nullptr, fbflag);
+}
+
+// Fallback bits of the systems (the workspace keeps them for later solves).
+int write_fbits(const Ctx& c, const std::vector<char>& fb)
+{
+    std::vector<int32_t> h(fb.begin(), fb.end());
+    if (hipMemcpyAsync(c.ws + c.p->off_fbits, h.data(), sizeof(int32_t) * h.size(),
+                       hipMemcpyHostToDevice, c.st) != hipSuccess ||
+        hipStreamSynchronize(c.st) != hipSuccess)
+        return CRSOLVE_EHIP;
+    return CRSOLVE_OK;
+}
+
+int read_fbits(const Ctx& c, std::vector<char>& fb)
+{
+    std::vector<int32_t> h(c.p->batch);
+    if (hipMemcpyAsync(h.data(), c.ws + c.p->off_fbits, sizeof(int32_t) * h.size(),
+                       hipMemcpyDeviceToHost, c.st) != hipSuccess ||
+        hipStreamSynchronize(c.st) != hipSuccess)
+        return CRSOLVE_EHIP;
+    fb.assign(h.begin(), h.end());
+    return CRSOLVE_OK;
+}
+
+int read_flags(const Ctx& c, std::vector<unsigned long long>& fl)
+{
+    fl.resize(c.p->batch);
+    if (hipMemcpyAsync(fl.data(), c.flags, sizeof(unsigned long long) * fl.size(),
+                       hipMemcpyDeviceToHost, c.st) != hipSuccess ||
+        hipStreamSynchronize(c.st) != hipSuccess)
+        return CRSOLVE_EHIP;
+    return CRSOLVE_OK;
+}
+
+// After the refinement: the systems marked in fb are solved by their FP64
+// plans; the residuals of those are measured for the record; the info
+// records get {corrections, residual} (no correction counts for a fallback
+// system) and the workspace keeps the fallback bits.
+int finish_refine(const crsolve_plan* p, const Ctx& c, const void* A, const void* B,
+                  const void* y, void* x, crsolve_info* info, const std::vector<char>& fb,
+                  std::vector<double>& tab)
+{
+    int rc;
+    bool any = false;
     for (int s = 0; s < p->batch; ++s)
-        tab[2 * s + 1] = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
-    return write_refine_info(c, info, tab);
+        if (fb[s]) {
+            fallback_sys(p, c.ws, c.st, s, A, B, y, x, info, 1);
+            any = true;
+        }
+    if (any) {
+        residual(c, A, B, x, y, false);
+        std::vector<double> nh;
+        if ((rc = read_norms(c, nh)))
+            return rc;
+        for (int s = 0; s < p->batch; ++s)
+            if (fb[s]) {
+                tab[2 * s] = 0;
+                tab[2 * s + 1] = rel_of(nh, s);
+            }
+    }
+    if ((rc = write_fbits(c, fb)))
+        return rc;
+    if ((rc = write_refine_info(c, info, tab)))
+        return rc;
+    return last_err();
 }
 
 // crsolve_factor_solve of the mixed form: the fused first pass, one
-// synchronization for the breakdown flags and the residual norms, then either
-// the refinement passes or the FP64 fallback.
+// synchronization for the breakdown flags and the residual norms, the
+// refinement passes, then the FP64 fallback of the systems that need it.
 int factor_solve_refine(const crsolve_plan* p, const void* A, const void* B, const void* y,
                         void* x, char* ws, crsolve_info* info, hipStream_t st)
 {
@@ -1282,17 +1392,12 @@ int factor_solve_refine(const crsolve_plan* p, const void* A, const void* B, con
             return rc;
         enqueue_refine_fused(c, A, B, y, x);
     }
-    std::vector<unsigned long long> fl(p->batch);
-    if (hipMemcpyAsync(fl.data(), c.flags, sizeof(unsigned long long) * p->batch,
-                       hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return CRSOLVE_EHIP;
-    bool failed = false;
-    for (unsigned long long f : fl)
-        failed |= f != crs::kNoFail;
-    p->use_fb = failed;
-    if (failed)
-        return fallback_fs(p, c, A, B, y, x, info);
+    std::vector<unsigned long long> fl;
+    if ((rc = read_flags(c, fl)))
+        return rc;
+    std::vector<char> fb(p->batch, 0);
+    for (int s = 0; s < p->batch; ++s)
+        fb[s] = fl[s] != crs::kNoFail;
     finalize(c, info, 0);
     auto pass = [&](bool first) -> int {
         if (!p->graphs_on) {
@@ -1302,14 +1407,20 @@ int factor_solve_refine(const crsolve_plan* p, const void* A, const void* B, con
         return with_graph(p, gkey(3, {A, B, y, x, ws}), ws, st,
                           [&](const Ctx& g) { enqueue_refine_pass(g, A, B, y, x, first); });
     };
-    if ((rc = refine_iterate(p, c, pass, info)))
+    std::vector<double> tab;
+    if ((rc = refine_iterate(p, c, pass, fb, tab)))
         return rc;
-    return last_err();
+    return finish_refine(p, c, A, B, y, x, info, fb, tab);
 }
 
-// FP32 factorization with FP64 tail; on breakdown, the FP64 plan takes over.
+// FP32 factorization with FP64 tail.  Systems whose FP32 factorization broke
+// down are factored by their FP64 plans (for their info record; a later
+// solve redoes it, as the fallback region holds one system at a time) and
+// marked for the FP64 path.  With verdict64 (the definiteness test) every
+// system is factored in FP64 and its record is the FP64 one; a system that
+// fails there is marked too.
 int factor_refine(const crsolve_plan* p, const void* A, const void* B, char* ws,
-                  crsolve_info* info, hipStream_t st)
+                  crsolve_info* info, hipStream_t st, bool verdict64)
 {
     Ctx c = make_ctx(p, ws, st);
     int rc;
@@ -1323,26 +1434,29 @@ int factor_refine(const crsolve_plan* p, const void* A, const void* B, char* ws,
             return rc;
         enqueue_refine_factor(c, A, B);
     }
-    std::vector<unsigned long long> fl(p->batch);
-    if (hipMemcpyAsync(fl.data(), c.flags, sizeof(unsigned long long) * p->batch,
-                       hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return CRSOLVE_EHIP;
-    bool failed = false;
-    for (unsigned long long f : fl)
-        failed |= f != crs::kNoFail;
-    p->use_fb = failed;
-    if (!failed) {
-        finalize(c, info, 0);
-        return last_err();
-    }
-    const crsolve_plan* q = p->fb.get();
-    Ctx cf = make_ctx(q, ws + p->off_fb, st);
-    if ((rc = upload(q, cf.ws, st)))
+    std::vector<unsigned long long> fl;
+    if ((rc = read_flags(c, fl)))
         return rc;
-    init_flags(cf);
-    levels_down(cf, A, B, nullptr, 1, 0);
-    finalize(cf, info, 1);
+    finalize(c, info, 0);
+    std::vector<char> fb(p->batch, 0);
+    for (int s = 0; s < p->batch; ++s) {
+        const bool f32fail = fl[s] != crs::kNoFail;
+        if (!f32fail && !verdict64)
+            continue;
+        fallback_sys(p, ws, st, s, A, B, nullptr, nullptr, info, f32fail ? 1 : 0);
+        fb[s] = f32fail;
+        if (verdict64 && !f32fail) {
+            // the FP64 verdict of a system the FP32 factorization passed
+            unsigned long long f64 = 0;
+            if (hipMemcpyAsync(&f64, ws + p->off_fb + p->fbs[s]->off_flags, sizeof(f64),
+                               hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return CRSOLVE_EHIP;
+            fb[s] = f64 != crs::kNoFail;
+        }
+    }
+    if ((rc = write_fbits(c, fb)))
+        return rc;
     return last_err();
 }
 
@@ -1353,24 +1467,10 @@ int solve_refine(const crsolve_plan* p, char* ws, const void* A, const void* B, 
     int rc = upload(p, ws, st);
     if (rc)
         return rc;
-    std::vector<double> nh, tab(2 * p->batch, 0.0);
-    if (p->use_fb) {
-        // FP64 factors: one solve, then the residual for the record
-        const crsolve_plan* q = p->fb.get();
-        Ctx cf = make_ctx(q, ws + p->off_fb, st);
-        if ((rc = upload(q, cf.ws, st)))
-            return rc;
-        levels_down(cf, nullptr, nullptr, y, 0, 1);
-        levels_up(cf, x);
-        residual(c, A, B, x, y, false);
-        if ((rc = read_norms(c, nh)))
-            return rc;
-        for (int s = 0; s < p->batch; ++s)
-            tab[2 * s + 1] = nh[2 * s + 1] > 0 ? std::sqrt(nh[2 * s] / nh[2 * s + 1]) : 0.0;
-        if ((rc = write_refine_info(c, info, tab)))
-            return rc;
-        return last_err();
-    }
+    std::vector<char> fb;
+    if ((rc = read_fbits(c, fb)))
+        return rc;
+    finalize(c, info, 0);
     auto pass = [&](bool first) -> int {
         if (!p->graphs_on) {
             enqueue_refine_pass(c, A, B, y, x, first);
@@ -1382,9 +1482,10 @@ int solve_refine(const crsolve_plan* p, char* ws, const void* A, const void* B, 
     // x_0 = A^{-1} y with the mixed factors, then its residual
     if ((rc = pass(true)))
         return rc;
-    if ((rc = refine_iterate(p, c, pass, info)))
+    std::vector<double> tab;
+    if ((rc = refine_iterate(p, c, pass, fb, tab)))
         return rc;
-    return last_err();
+    return finish_refine(p, c, A, B, y, x, info, fb, tab);
 }
 
 int validate(const crsolve_desc* d)
@@ -1452,15 +1553,21 @@ crsolve_plan* new_plan(const crsolve_desc* d, crsolve_precision prec, int* rc)
     p->toty = oy;
     p->totN = on;
     if (prec == CRSOLVE_PREC_FP32_REFINE) {
-        crsolve_desc dn = *d;
-        dn.precision = CRSOLVE_PREC_NATIVE;
-        dn.dtype = CRSOLVE_C128;
-        p->fb.reset(new_plan(&dn, CRSOLVE_PREC_NATIVE, rc));
-        if (!p->fb) {
-            delete p;
-            return nullptr;
+        for (int s = 0; s < p->batch; ++s) {
+            crsolve_desc dn = *d;
+            dn.batch = 1;
+            dn.N = d->N + s;
+            dn.m = d->m + s;
+            dn.k = d->k + s;
+            dn.precision = CRSOLVE_PREC_NATIVE;
+            dn.dtype = CRSOLVE_C128;
+            p->fbs.emplace_back(new_plan(&dn, CRSOLVE_PREC_NATIVE, rc));
+            if (!p->fbs.back()) {
+                delete p;
+                return nullptr;
+            }
+            p->fbs.back()->timing_parent = p;
         }
-        p->fb->timing_parent = p;
     }
     *rc = build_plan(p);
     if (*rc != CRSOLVE_OK) {
@@ -1571,8 +1678,6 @@ int crsolve_set_graphs(crsolve_plan* p, int enable)
     p->graphs_on = enable != 0;
     if (!enable)
         p->drop_graphs();
-    if (p->fb)
-        p->fb->graphs_on = false;
     return CRSOLVE_OK;
 }
 
@@ -1656,6 +1761,7 @@ int crsolve_autotune(crsolve_plan* p, const void* A, const void* B, const void* 
             }
     p->drop_graphs();
     p->graphs_on = graphs;
+    p->mark_factored(ws);
     if (out.size() + 1 > cap)
         return CRSOLVE_EINVAL;
     std::memcpy(choice, out.c_str(), out.size() + 1);
@@ -1681,8 +1787,9 @@ const char* crsolve_error_string(int code)
     }
 }
 
-int crsolve_factor(crsolve_plan* p, const void* A, const void* B, void* ws, size_t ws_bytes,
-                   crsolve_info* info, void* stream)
+namespace {
+int factor_entry(crsolve_plan* p, const void* A, const void* B, void* ws, size_t ws_bytes,
+                 crsolve_info* info, void* stream, bool verdict64)
 {
     if (!p)
         return CRSOLVE_EINVAL;
@@ -1693,22 +1800,35 @@ int crsolve_factor(crsolve_plan* p, const void* A, const void* B, void* ws, size
         return rc;
     if (!aligned(A, io_esz(p)) || (any_B(p) && !aligned(B, io_esz(p))))
         return CRSOLVE_EINVAL;
-    if (p->prec == CRSOLVE_PREC_FP32_REFINE)
-        return factor_refine(p, A, B, (char*)ws, info, (hipStream_t)stream);
-    Ctx c = make_ctx(p, ws, stream);
-    if ((rc = upload(p, c.ws, c.st)))
-        return rc;
-    init_flags(c);
-    levels_down(c, A, B, nullptr, 1, 0);
-    finalize(c, info, 0);
-    return last_err();
+    if (p->prec == CRSOLVE_PREC_FP32_REFINE) {
+        rc = factor_refine(p, A, B, (char*)ws, info, (hipStream_t)stream, verdict64);
+    } else {
+        Ctx c = make_ctx(p, ws, stream);
+        if ((rc = upload(p, c.ws, c.st)))
+            return rc;
+        init_flags(c);
+        levels_down(c, A, B, nullptr, 1, 0);
+        finalize(c, info, 0);
+        rc = last_err();
+    }
+    if (rc == CRSOLVE_OK)
+        p->mark_factored(ws);
+    return rc;
+}
+} // namespace
+
+int crsolve_factor(crsolve_plan* p, const void* A, const void* B, void* ws, size_t ws_bytes,
+                   crsolve_info* info, void* stream)
+{
+    return factor_entry(p, A, B, ws, ws_bytes, info, stream, false);
 }
 
 int crsolve_check_hpd(crsolve_plan* p, const void* A, const void* B, void* ws, size_t ws_bytes,
                       crsolve_info* info, void* stream)
 {
-    // the factorization is the test: its flag is the verdict
-    return crsolve_factor(p, A, B, ws, ws_bytes, info, stream);
+    // the factorization is the test: its flag is the verdict (FP64's for the
+    // mixed form)
+    return factor_entry(p, A, B, ws, ws_bytes, info, stream, true);
 }
 
 int crsolve_solve(const crsolve_plan* p, void* ws, size_t ws_bytes, const void* A, const void* B,
@@ -1721,6 +1841,8 @@ int crsolve_solve(const crsolve_plan* p, void* ws, size_t ws_bytes, const void* 
     int rc = check_ws(p, ws, ws_bytes);
     if (rc)
         return rc;
+    if (!p->is_factored(ws))
+        return CRSOLVE_ESTATE;
     if (!aligned(y, io_esz(p)) || !aligned(x, io_esz(p)))
         return CRSOLVE_EINVAL;
     if (p->prec == CRSOLVE_PREC_FP32_REFINE) {
@@ -1733,6 +1855,7 @@ int crsolve_solve(const crsolve_plan* p, void* ws, size_t ws_bytes, const void* 
         return rc;
     levels_down(c, nullptr, nullptr, y, 0, 1);
     levels_up(c, x);
+    finalize(c, info, 0);
     return last_err();
 }
 
@@ -1747,18 +1870,22 @@ int crsolve_factor_solve(crsolve_plan* p, const void* A, const void* B, const vo
     const size_t es = io_esz(p);
     if (!aligned(A, es) || (any_B(p) && !aligned(B, es)) || !aligned(y, es) || !aligned(x, es))
         return CRSOLVE_EINVAL;
-    if (p->prec == CRSOLVE_PREC_FP32_REFINE)
-        return factor_solve_refine(p, A, B, y, x, (char*)ws, info, (hipStream_t)stream);
-    if (p->graphs_on) {
+    if (p->prec == CRSOLVE_PREC_FP32_REFINE) {
+        rc = factor_solve_refine(p, A, B, y, x, (char*)ws, info, (hipStream_t)stream);
+    } else if (p->graphs_on) {
         rc = with_graph(p, gkey(0, {A, B, y, x, ws, info}), (char*)ws, (hipStream_t)stream,
                         [&](const Ctx& g) { enqueue_native_fs(g, A, B, y, x, info); });
-        return rc ? rc : last_err();
+        rc = rc ? rc : last_err();
+    } else {
+        Ctx c = make_ctx(p, ws, stream);
+        if ((rc = upload(p, c.ws, c.st)))
+            return rc;
+        enqueue_native_fs(c, A, B, y, x, info);
+        rc = last_err();
     }
-    Ctx c = make_ctx(p, ws, stream);
-    if ((rc = upload(p, c.ws, c.st)))
-        return rc;
-    enqueue_native_fs(c, A, B, y, x, info);
-    return last_err();
+    if (rc == CRSOLVE_OK && p->sched == CRSOLVE_SCHED_CR)
+        p->mark_factored(ws);
+    return rc;
 }
 
 int crsolve_backward(const crsolve_plan* p, void* ws, size_t ws_bytes, const void* x,
@@ -1771,6 +1898,8 @@ int crsolve_backward(const crsolve_plan* p, void* ws, size_t ws_bytes, const voi
     int rc = check_ws(p, ws, ws_bytes);
     if (rc)
         return rc;
+    if (!p->is_factored(ws))
+        return CRSOLVE_ESTATE;
     const size_t es = io_esz(p);
     if (!aligned(x, es) || !aligned(grad_x, es) || !aligned(grad_y, es) || !aligned(grad_A, es) ||
         (any_B(p) && !aligned(grad_B, es)))

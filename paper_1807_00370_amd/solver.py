@@ -232,6 +232,15 @@ class CRSolve(torch.autograd.Function):
     forms grad y = lam, grad A_j = -lam_j x_j^H,
     grad B_j = -(lam_{j+1} x_j^H + x_{j+1} lam_j^H) in the library.
     Raises ``torch.linalg.LinAlgError`` when A is not positive definite.
+
+    grad A_j is the block of the dense gradient -lam x^H, which is the
+    gradient of the loss for Hermitian perturbations of A_j.  The forward
+    pass reads only the lower triangle and the real diagonal of the tensor
+    A_j, so for a raw, unconstrained leaf tensor A the gradient of what the
+    solver actually computes is tril(G, -1) + tril(G^H, -1) + diag(Re G)
+    with G = grad A_j (upper triangle zero), not G itself: build A_j from a
+    Hermitian parametrization (e.g. (M + M^H) / 2) when differentiating
+    through A, or project the returned gradient that way.
     """
 
     @staticmethod

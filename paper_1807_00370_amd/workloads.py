@@ -24,6 +24,10 @@ Recipes (the synthetic stand-ins for the paper's unspecified workloads):
   ``shift`` subtracts ``shift_scale * (||B_{j-1}|| + ||B_j|| + margin) I``
   (``shift_scale=2`` makes every diagonal block indefinite).
   ``ill=True`` replaces the margin 1 by ``1e-5 (||B_{j-1}|| + ||B_j||)``.
+  ``diag_shift=c`` subtracts ``c I`` from every ``A_j`` afterwards (the
+  calibrated condition numbers of the precision workload use the shifts in
+  ``tests/golden/kappa_shifts.json``, computed from the oracle's extreme
+  eigenvalues by the script beside it).
 * ``poisson``: the real 2D five-point Laplacian on an m x N grid,
   ``A_j = tridiag(-1, 4, -1)``, ``B_j = -I``, with ``y`` an eigenvector
   ``y[j, a] = sin(p a pi/(m+1)) sin(q j pi/(N+1))`` (1-based a, j).
@@ -90,7 +94,7 @@ class System:
 
 
 def random_hpd(N: int, m: int, k: int, seed: int, *, margin: float = 1.0,
-               shift_scale: float = 0.0, ill: bool = False,
+               shift_scale: float = 0.0, ill: bool = False, diag_shift: float = 0.0,
                with_W: bool = False, chunk: int = 8192) -> System:
     """The block diagonally dominant Hermitian positive definite generator."""
     if N < 1 or m < 1 or k < 1:
@@ -117,12 +121,13 @@ def random_hpd(N: int, m: int, k: int, seed: int, *, margin: float = 1.0,
         blk /= m
         blk = 0.5 * (blk + np.conj(np.swapaxes(blk, 1, 2)))
         idx = np.arange(m)
-        blk[:, idx, idx] = blk[:, idx, idx].real + diag[s:e, None]
+        blk[:, idx, idx] = blk[:, idx, idx].real + diag[s:e, None] - diag_shift
         A[s:e] = blk
     y = _cnormal(rng, (N, m, k), 1.0)
     W = _cnormal(rng, (N, m, k), 1.0) if with_W else None
     return System(A, B, y, W, dict(kind="random_hpd", N=N, m=m, k=k, seed=seed,
-                                   margin=margin, shift_scale=shift_scale, ill=ill))
+                                   margin=margin, shift_scale=shift_scale, ill=ill,
+                                   diag_shift=diag_shift))
 
 
 def poisson(N: int, m: int, p: int = 1, q: int = 1) -> System:
@@ -179,12 +184,14 @@ def _pack_one(i):
     return i
 
 
-def batch_packed(shapes, seed: int, workers: int = 1):
+def batch_packed(shapes, seed: int, workers: int = 1, shared: bool = False):
     """The systems of ``batch_systems(shapes, seed)`` packed back to back:
     flat (A, B, y) arrays in the library's batch layout.  With ``workers`` > 1
     the systems are drawn by forked worker processes into shared memory
     (same values: every system has its own generator).  Fork only from a
-    process that has not initialised a GPU."""
+    process that has not initialised a GPU.  With ``shared`` (and workers >
+    1) the arrays are views of the shared-memory segments, returned with a
+    ``release()`` callable that frees them (no copy of the inputs)."""
     offA, offB, offy = [0], [0], [0]
     for N, m, k in shapes:
         offA.append(offA[-1] + N * m * m)
@@ -209,14 +216,66 @@ def batch_packed(shapes, seed: int, workers: int = 1):
         with mp.get_context("fork").Pool(workers) as pool:
             for _ in pool.imap_unordered(_pack_one, range(len(shapes))):
                 pass
+        if shared:
+            views = [np.ndarray((tot[n],), dtype=np.complex128, buffer=shms[n].buf)
+                     for n in ("A", "B", "y")]
+
+            def release():
+                views.clear()
+                for sh in shms.values():
+                    sh.close()
+                    sh.unlink()
+            _PACK.clear()
+            return views[0], views[1], views[2], release
         out = [np.ndarray((tot[n],), dtype=np.complex128, buffer=shms[n].buf).copy()
                for n in ("A", "B", "y")]
-    finally:
+    except BaseException:
         for sh in shms.values():
             sh.close()
             sh.unlink()
         _PACK.clear()
+        raise
+    for sh in shms.values():
+        sh.close()
+        sh.unlink()
+    _PACK.clear()
     return tuple(out)
+
+
+def _draw_one(args):
+    from threadpoolctl import threadpool_limits
+    i, N, m, k, seed = args
+    with threadpool_limits(1):
+        q = random_hpd(N, m, k, seed * 1000 + i)
+    return i, q.A, q.B, q.y
+
+
+class BatchStream:
+    """The systems of ``batch_systems(shapes, seed)`` drawn by forked worker
+    processes and handed to the caller one by one (``for i, A, B, y in
+    stream``), so that a batch larger than host memory can be copied into
+    packed device arrays system by system.  Create it before the calling
+    process initialises a GPU (the workers are forked at construction)."""
+
+    def __init__(self, shapes, seed: int, workers: int):
+        import multiprocessing as mp
+        self.shapes = list(shapes)
+        self.seed = seed
+        self.pool = mp.get_context("fork").Pool(max(1, workers))
+        self.offA, self.offB, self.offy = [0], [0], [0]
+        for N, m, k in self.shapes:
+            self.offA.append(self.offA[-1] + N * m * m)
+            self.offB.append(self.offB[-1] + (N - 1) * m * m)
+            self.offy.append(self.offy[-1] + N * m * k)
+
+    def __iter__(self):
+        jobs = [(i, N, m, k, self.seed) for i, (N, m, k) in enumerate(self.shapes)]
+        try:
+            for rec in self.pool.imap_unordered(_draw_one, jobs):
+                yield rec
+        finally:
+            self.pool.close()
+            self.pool.join()
 
 
 # The named workloads (sizes as the paper's problem statement instantiates them)

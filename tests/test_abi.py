@@ -50,3 +50,45 @@ def test_null_pointers_rejected_without_device_work():
     assert lib.crsolve_factor(p._h, fake, fake, fake, p.ws_bytes - 1, None, None) == \
         _lib.EWORKSPACE
     assert lib.crsolve_factor(None, fake, fake, fake, p.ws_bytes, None, None) == _lib.EINVAL
+
+
+def test_solve_before_factor_is_a_state_error():
+    """crsolve_solve / crsolve_backward on a workspace the plan never factored
+    return CRSOLVE_ESTATE before any device work (the pointers are aligned
+    and never dereferenced)."""
+    import ctypes
+    lib = _lib.load()
+    fake = ctypes.c_void_p(1 << 20)
+    for prec in (_lib.PREC_NATIVE, _lib.PREC_FP32_REFINE):
+        p = _lib.Plan([16], [8], [2], precision=prec)
+        assert lib.crsolve_solve(p._h, fake, p.ws_bytes, fake, fake, fake, fake, None,
+                                 None) == _lib.ESTATE
+    p = _lib.Plan([16], [8], [2])
+    assert lib.crsolve_backward(p._h, fake, p.ws_bytes, fake, fake, fake, fake, fake,
+                                None) == _lib.ESTATE
+    # the size check still comes first
+    assert lib.crsolve_solve(p._h, fake, p.ws_bytes - 1, None, None, fake, fake, None,
+                             None) == _lib.EWORKSPACE
+
+
+def test_block_size_limits_match_header():
+    """1 <= m <= 256; N <= 2^24 when m > 64 (host-only plan creation)."""
+    _lib.Plan([4], [256], [1])
+    _lib.Plan([1 << 24], [65], [1])
+    with pytest.raises(_lib.CrsolveError) as e:
+        _lib.Plan([(1 << 24) + 1], [65], [1])
+    assert e.value.code == _lib.EUNSUPPORTED
+    hdr = open(os.path.join(ROOT, "include", "crsolve.h")).read()
+    assert "1 <= m <= 256" in hdr and "m <= 64" not in hdr
+
+
+def test_refine_fallback_region_is_one_system():
+    """The mixed form reserves an FP64 fallback region for its largest
+    system, not a second plan over the whole batch."""
+    shapes = [(2048, 32, 4)] + [(256, 8, 1)] * 40
+    Ns, ms, ks = zip(*shapes)
+    mixed = _lib.Plan(Ns, ms, ks, precision=_lib.PREC_FP32_REFINE).ws_bytes
+    big64 = _lib.Plan([2048], [32], [4]).ws_bytes
+    whole64 = _lib.Plan(Ns, ms, ks).ws_bytes
+    assert mixed < whole64 + big64
+    assert mixed >= big64

@@ -142,3 +142,29 @@ def test_batch_512_ragged_mixed_precision_graphs(tdev):
     assert (rec["status"] == 0).all() and (rec["fp64_fallback"] == 0).all()
     assert (rec["rel_residual"] <= 1e-12).all()
     _check_all(systems, _split(x, systems), tol=1e-10)
+
+
+@pytest.mark.parametrize("form", ["fp32_refine", "fp64"])
+def test_stated_range_batch(tdev, form):
+    """The first 32 systems of the stated batch (N = 2 U{128..4096}, m in
+    {8, 16, 32, 64}, k in {1, 4, 16}, the same seeds as the benchmark), one
+    plan, graph replay: every system against the FP64 oracle element by
+    element and by its residual."""
+    torch, dev = tdev
+    shapes = W.batch_shapes(W.BATCH_COUNT, W.config_seed(3))[:32]
+    print("case stated batch %s, %d systems, %d block rows" % (
+        form, len(shapes), sum(q[0] for q in shapes)), flush=True)
+    systems = W.batch_systems(shapes, W.config_seed(3))
+    A, B, y = (torch.from_numpy(v).to(dev) for v in _pack(systems))
+    kw = dict(precision="fp32_refine", rtol=1e-12, max_refine=30, fp64_tail_blocks=8) \
+        if form == "fp32_refine" else {}
+    sol = _solver(torch, dev, systems, **kw)
+    sol.set_graphs(True)
+    x = sol.factor_solve(A, B, y)
+    x = sol.factor_solve(A, B, y)  # a replay of the recorded graph
+    torch.cuda.synchronize()
+    info = sol.info_host()
+    assert (info["status"] == 0).all()
+    if form == "fp32_refine":
+        assert (info["rel_residual"] <= 1e-12).all()
+    _check_all(systems, _split(x.cpu().numpy(), systems))

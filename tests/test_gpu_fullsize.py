@@ -74,3 +74,60 @@ def test_adjoint_full_size(tdev, dt):
     assert _rel(A.grad.cpu().numpy(), gA) <= tol
     assert _rel(B.grad.cpu().numpy(), gB) <= tol
     assert _rel(y.grad.cpu().numpy(), lam) <= tol
+
+
+def test_pcr_full_size(tdev):
+    """Algorithm 1 at the full large-system size N = 65536, m = 32, k = 16
+    (every level above 1024 blocks runs the populated-level kernels)."""
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import Solver
+    print("case pcr full N=65536 m=32 k=16", flush=True)
+    s = W.random_hpd(**W.LARGE, seed=W.config_seed(1))
+    A, B, y = (torch.from_numpy(v).to(dev) for v in (s.A, s.B, s.y))
+    sol = Solver([s.N], [s.m], [s.k], device=dev, schedule="pcr")
+    x = sol.factor_solve(A, B, y).cpu().numpy()
+    rec = sol.info_host()[0]
+    assert int(rec["status"]) == 0
+    assert oracle.rel_residual(s.A, s.B, x, s.y) <= 1e-12
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert io["status"] == 0
+    assert _rel(x, xo) <= 1e-11
+
+
+def _kappa_shift(kappa):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kappa_shifts.json")
+    with open(path) as fh:
+        return json.load(fh)["shifts"]["%g" % kappa]
+
+
+@pytest.mark.parametrize("kappa", [1e5, 1e6])
+def test_refine_calibrated_kappa_full_size(tdev, kappa):
+    """The precision workload shifted to kappa = 1e5 and 1e6 (shift from
+    tests/golden/kappa_shifts.json, computed with the oracle only): the
+    mixed form certifies ||y - A x|| / ||y|| <= 1e-12, either by refinement
+    or by its FP64 fallback, and x agrees with the FP64 oracle within
+    kappa * 200 u (both are backward stable; forward errors scale with
+    kappa)."""
+    torch, dev = tdev
+    from paper_1807_00370_amd.solver import Solver
+    c = _kappa_shift(kappa)
+    print("case refine kappa=%g shift=%.15g" % (kappa, c), flush=True)
+    s = W.random_hpd(**W.LARGE, seed=W.config_seed(2), diag_shift=c)
+    A, B, y = (torch.from_numpy(v).to(dev) for v in (s.A, s.B, s.y))
+    sol = Solver([s.N], [s.m], [s.k], precision="fp32_refine", device=dev, rtol=1e-12,
+                 max_refine=30, fp64_tail_blocks=8)
+    sol.set_graphs(True)
+    x = sol.factor_solve(A, B, y).cpu().numpy()
+    rec = sol.info_host()[0]
+    print("kappa=%g: refine_iters=%d fp64_fallback=%d rel_residual=%.3e" % (
+        kappa, rec["refine_iters"], rec["fp64_fallback"], rec["rel_residual"]), flush=True)
+    assert int(rec["status"]) == 0
+    res = oracle.rel_residual(s.A, s.B, x, s.y)
+    assert res <= 1e-12
+    assert abs(float(rec["rel_residual"]) - res) <= 0.1 * res + 1e-16
+    assert int(rec["fp64_fallback"]) == 1 or int(rec["refine_iters"]) >= 1
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert io["status"] == 0
+    assert _rel(x, xo) <= kappa * 200 * 2.0 ** -53

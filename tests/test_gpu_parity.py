@@ -280,3 +280,35 @@ def test_invalid_arguments(torch_dev):
                                     ctypes.c_void_p(ws.data_ptr()),
                                     ctypes.c_void_p(ws.data_ptr()), p.ws_bytes - 1, None, None)
     assert rc == _lib.EWORKSPACE
+
+
+# Algorithm 1 where its levels hold more than 1024 blocks (the populated-level
+# kernels: one-wave reduction, unsplit elimination) and, for blocks above 64,
+# at least 256 blocks (one-wave-per-strip tiled substitutions).  x is unique,
+# so the one-sided oracle serves as the reference at the larger sizes; the
+# flag record is compared with the oracle's Algorithm 1.
+@pytest.mark.parametrize("N,m,k", [(4096, 32, 16), (8192, 16, 4), (2500, 8, 3), (512, 80, 4),
+                                   (600, 128, 2)])
+def test_pcr_populated_levels_match_oracle(torch_dev, N, m, k):
+    torch, dev = torch_dev
+    print("case pcr populated N=%d m=%d k=%d" % (N, m, k), flush=True)
+    s = W.random_hpd(N, m, k, 8100 + N + m + k)
+    x, info = _solve(torch, dev, s, schedule="pcr")
+    assert info == dict(status=0, level=-1, block=-1)
+    xo, io = oracle.solve_cr(s.A, s.B, s.y)
+    assert io["status"] == 0
+    assert _rel(x, xo) <= TOL64
+    assert oracle.rel_residual(s.A, s.B, x, s.y) <= RES64
+
+
+def test_pcr_populated_indefinite_twin(torch_dev):
+    """The shifted generator at N = 4096: every diagonal block indefinite, so
+    Algorithm 1 breaks down at level 0, block 1, with populated launches."""
+    torch, dev = torch_dev
+    for m, k in ((4, 1), (32, 2)):
+        print("case pcr twin N=4096 m=%d" % m, flush=True)
+        t = W.random_hpd(4096, m, k, W.config_seed(0, 5) + m, shift_scale=2.0)
+        x, info = _solve(torch, dev, t, schedule="pcr")
+        _, io = oracle.solve_pcr(t.A, t.B, t.y) if m == 4 else oracle.solve_cr(t.A, t.B, t.y)
+        assert info == io == dict(status=1, level=0, block=1)
+        assert np.isnan(x).all()

@@ -336,3 +336,30 @@ def test_generator_is_hpd_and_seeded():
     assert np.linalg.eigvalsh(dense(s1.A, s1.B))[0] > 0
     for a in s1.A:
         assert np.array_equal(a, a.conj().T)
+
+
+@pytest.mark.parametrize("N,m,k", [(1, 3, 2), (2, 4, 1), (7, 5, 3), (12, 8, 4)])
+def test_residual_matches_dense_product(N, m, k):
+    """cro_residual against y - D x with D assembled from the blocks (Eq.
+    (Axb)), for an x that is not the solution, and with noise in the strict
+    upper triangle and in Im(diag) of every A_j that the Hermitian reading
+    (lower triangle, real diagonal) must ignore."""
+    rng = np.random.default_rng(4242 + N * m + k)
+    s = W.random_hpd(N, m, k, 600 + N + m + k)
+    A = s.A.copy()
+    for j in range(N):
+        up = np.triu(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)), 1)
+        A[j] += up
+        A[j][np.diag_indices(m)] += 1j * rng.standard_normal(m)
+    x = rng.standard_normal((N, m, k)) + 1j * rng.standard_normal((N, m, k))
+    r = oracle.residual(A, s.B, x, s.y)
+    D = dense(A, s.B)
+    ref = stack(s.y) - D @ stack(x)
+    assert np.max(np.abs(stack(r) - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+    # a plainly wrong reading (the full block with its upper-triangle noise) differs
+    Dfull = D.copy()
+    for j in range(N):
+        Dfull[j * m:(j + 1) * m, j * m:(j + 1) * m] = A[j]
+    assert np.max(np.abs(stack(r) - (stack(s.y) - Dfull @ stack(x)))) > 1e-3
+    rel = oracle.rel_residual(A, s.B, x, s.y)
+    assert abs(rel - np.linalg.norm(ref) / np.linalg.norm(stack(s.y))) <= 1e-14 * rel
