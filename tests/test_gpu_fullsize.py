@@ -94,12 +94,16 @@ def test_pcr_full_size(tdev):
     assert _rel(x, xo) <= 1e-11
 
 
-def _kappa_shift(kappa):
+def _kappa_rec():
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kappa_shifts.json")
     with open(path) as fh:
-        return json.load(fh)["shifts"]["%g" % kappa]
+        return json.load(fh)
+
+
+def _kappa_shift(kappa):
+    return _kappa_rec()["shifts"]["%g" % kappa]
 
 
 @pytest.mark.parametrize("kappa", [1e5, 1e6])
@@ -126,7 +130,12 @@ def test_refine_calibrated_kappa_full_size(tdev, kappa):
     assert int(rec["status"]) == 0
     res = oracle.rel_residual(s.A, s.B, x, s.y)
     assert res <= 1e-12
-    assert abs(float(rec["rel_residual"]) - res) <= 0.1 * res + 1e-16
+    # the library's and the oracle's residuals differ by their own rounding,
+    # |fl(r) - r| <~ m u ||A||_2 ||x|| (||A||_2 = lambda_max - c), which at
+    # kappa = 1e6 is no longer small against ||r||
+    normA = _kappa_rec()["lambda_max"] - c
+    slack = s.m * 2.0 ** -53 * normA * np.linalg.norm(x) / np.linalg.norm(s.y)
+    assert abs(float(rec["rel_residual"]) - res) <= 0.1 * res + slack
     assert int(rec["fp64_fallback"]) == 1 or int(rec["refine_iters"]) >= 1
     xo, io = oracle.solve_cr(s.A, s.B, s.y)
     assert io["status"] == 0
