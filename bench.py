@@ -83,42 +83,54 @@ def levels(N: int):
     return out
 
 
-def pass_model(N, m, k, s_of_level, mat, rhs):
+def pass_model(N, m, k, s_of_level, mat, rhs, s_in0=None, upd=0):
     """Algorithmic bytes and flops of one pass over the levels, per kernel.
     Blocks above 64 split the elimination into the tiled Cholesky
     (k_potrf_big: read A_p lower, write L lower) and the tiled substitutions
-    (k_trsm_big: read L, B_p, B_{p-1}, y_p; write P, Q, g)."""
+    (k_trsm_big: read L, B_p, B_{p-1}, y_p; write P, Q, g).  s_in0: bytes per
+    element of the level-0 inputs A, B, y when they differ from the level's
+    own precision (the mixed form's FP32 level 0 reads the FP64 arrays);
+    upd: the mixed form's level-0 back substitution writes the FP64 x
+    (1: x = d, 2: x += d, which also reads x), for the eliminated and the
+    kept blocks."""
     mm, mk, T = m * m, m * k, m * (m + 1) // 2
     big = m > 64
     names = ("k_potrf_big", "k_trsm_big") if big else ("k_elim", "k_elim")
     tot = {kn: [0.0, 0.0] for kn in set(names) | {"k_reduce", "k_back"}}
     for lvl, (n, ne, nk, e_prev, e_next, k_right, k_f) in enumerate(levels(N)):
         s = s_of_level(n)
+        si = s_in0 if (lvl == 0 and s_in0) else s
         if mat:
-            tot[names[0]][0] += ne * 2 * T * s
+            tot[names[0]][0] += ne * T * (si + s)
             tot[names[0]][1] += 8 * ne * mm * m / 6
         b = f = 0.0
         if mat:
-            b += (e_prev + e_next) * 2 * mm + (ne * T if big else 0)
+            b += (e_prev + e_next) * mm * (si + s) + (ne * T * s if big else 0)
             f += (e_prev + e_next) * mm * m / 2
         if rhs:
-            b += ne * (2 * mk + (0 if mat else T))
+            b += ne * (mk * (si + s) + (0 if mat else T * s))
             f += ne * mk * m / 2
-        tot[names[1]][0] += b * s
+        tot[names[1]][0] += b
         tot[names[1]][1] += 8 * f
         b = f = 0.0
         if mat:
-            b += nk * (2 * T + mm) + k_right * mm + k_f * 2 * mm
+            b += nk * (T * (si + s) + mm * s) + k_right * mm * s + k_f * 2 * mm * s
             f += nk * mm * m / 2 + k_right * mm * m / 2 + k_f * mm * m
         if rhs:
-            b += nk * (2 * mk) + nk * mk + k_right * mk + (0 if mat else (nk + k_right) * mm)
+            b += nk * mk * (si + s) + nk * mk * s + k_right * mk * s + \
+                (0 if mat else (nk + k_right) * mm * s)
             f += nk * mk * m + k_right * mk * m
-        tot["k_reduce"][0] += b * s
+        tot["k_reduce"][0] += b
         tot["k_reduce"][1] += 8 * f
         if rhs:
-            b = ne * (T + 2 * mk) + (e_prev + e_next) * (mm + mk)
+            b = (ne * (T + mk) + (e_prev + e_next) * (mm + mk)) * s
+            if lvl == 0 and upd:
+                # x_p and the kept neighbour's x_{p+1} in FP64 (read too when x += d)
+                b += (ne + nk) * mk * 16 * (2 if upd == 2 else 1)
+            else:
+                b += ne * mk * s
             f = (e_prev + e_next) * mk * m + ne * mk * m / 2
-            tot["k_back"][0] += b * s
+            tot["k_back"][0] += b
             tot["k_back"][1] += 8 * f
     return tot
 
@@ -133,19 +145,20 @@ def add(a, b, scale=1.0):
 
 
 def step_model(form, N, m, k, iters=0):
-    """Per-kernel algorithmic [bytes, flops] of one step of a form."""
+    """Per-kernel algorithmic [bytes, flops] of one step of a form.  The mixed
+    form: the fused factor + first solve (level 0 reads the FP64 A, B, y and
+    assigns x), `iters` correction passes (level 0 reads the FP64 residual
+    and adds to x), and one FP64 residual per solve (read A_j lower, B_j,
+    x_j, y_j; write r_j in FP64)."""
     if form == "fp64":
         return pass_model(N, m, k, lambda n: 16, True, True)
     s_lvl = lambda n: 16 if n <= TAIL else 8
     tot = {}
-    add(tot, pass_model(N, m, k, s_lvl, True, False))
-    add(tot, pass_model(N, m, k, s_lvl, False, True), 1 + iters)
+    add(tot, pass_model(N, m, k, s_lvl, True, True, s_in0=16, upd=1))
+    if iters:
+        add(tot, pass_model(N, m, k, s_lvl, False, True, s_in0=16, upd=2), iters)
     mm, mk, T = m * m, m * k, m * (m + 1) // 2
-    # residuals in FP64 (one per solve) and conversions / updates
-    add(tot, {"k_residual": [N * (T + mm + 2 * mk) * 16 + N * mk * 8, 8 * N * 3 * mm * k]},
-        1 + iters)
-    add(tot, {"k_convert": [N * (T + mm) * (16 + 8) + N * mk * (16 + 8), 0.0]})
-    add(tot, {"k_update": [N * mk * (16 + 16 + 8), 0.0]}, 1 + iters)
+    add(tot, {"k_residual": [N * (T + mm + 3 * mk) * 16, 8 * N * 3 * mm * k]}, 1 + iters)
     return tot
 
 

@@ -68,6 +68,8 @@ struct Launch {
     bool userAB;     // matrix inputs are the caller's arrays
     bool userY;      // right-hand-side input is the caller's array
     bool userX;      // unknowns are written to the caller's x
+    bool in64;       // the level's inputs are FP64 (FP32 levels round on load)
+    bool upd;        // mixed form, level 0: corrections go into the FP64 x
 };
 
 struct CvtLaunch {
@@ -86,7 +88,9 @@ struct LevelSpec {
     int64_t oD = 0;                                                   // big blocks only
     int64_t oA = 0, oB = 0, oy = 0;                                   // inputs, level type
     bool userAB = false, userY = false, userX = false;
+    bool in64 = false, upd = false;
     int64_t ox = 0, xo = 0, xs = 1;
+    int64_t oU = 0;
 };
 
 // Algorithm 1 in place: levels run until 2^l >= N, when every block is
@@ -109,7 +113,6 @@ enum KernelId {
     KID_CONVERT,
     KID_RESIDUAL,
     KID_NORMS,
-    KID_UPDATE,
     KID_POTRF,
     KID_TRSM,
     KID_COUNT
@@ -117,7 +120,7 @@ enum KernelId {
 const char* const kKernelName[KID_COUNT] = {"k_elim",       "k_reduce",   "k_back",
                                             "k_grad",       "k_flags_init", "k_finalize",
                                             "k_convert",    "k_residual", "k_norms",
-                                            "k_update",     "k_potrf_big", "k_trsm_big"};
+                                            "k_potrf_big",  "k_trsm_big"};
 
 } // namespace
 
@@ -139,6 +142,7 @@ struct crsolve_plan {
     size_t off_flags = 0, off_segs = 0, off_jobs = 0, ws_bytes = 0;
     size_t off_part = 0, off_norms = 0, off_info = 0, off_fb = 0;
     size_t off_d32 = 0;   // refinement correction (complex FP32, like y)
+    size_t off_r64 = 0;   // refinement residual r = y - A x (complex FP64, like y)
     size_t off_fbits = 0; // refinement: int32 per system, 1 = solved by its FP64 plan
 
     std::vector<std::vector<LevelSpec>> lv; // per system
@@ -147,7 +151,6 @@ struct crsolve_plan {
     std::vector<CvtJob> jobs;
     std::vector<Launch> elim, reduce, back, grad, resid;
     int norm_seg0 = 0;
-    std::vector<CvtLaunch> cvt_factor0, cvt_solve0;
     std::vector<std::vector<CvtLaunch>> cvt_factor_sw, cvt_solve_sw, scatter_sw;
     int nlevels = 0;
 
@@ -248,7 +251,9 @@ struct Timed {
 
 unsigned grid_of(int64_t total) { return (unsigned)std::min<int64_t>(total, kMaxGrid); }
 
-template <class T>
+// Kernel dispatch per block-size class MT, element type T and level-input
+// type TI (TI = double for the FP32 levels that read FP64 inputs).
+template <class T, class TI = T>
 struct Disp {
     template <int MT>
     static void elim(const Launch& L, const Seg* segs, const void* inA, const void* inB,
@@ -256,19 +261,19 @@ struct Disp {
                      hipStream_t st, int variant, int nsplit)
     {
         if ((MT == 16 || MT == 32) && variant == 0) {
-            hipLaunchKernelGGL((crs::k_elim_mf<T, (MT == 16 || MT == 32) ? MT : 16>),
+            hipLaunchKernelGGL((crs::k_elim_mf<T, (MT == 16 || MT == 32) ? MT : 16, TI>),
                                dim3((unsigned)(L.total * nsplit)), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, nsplit, (const cx<T>*)inA,
-                               (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+                               segs + L.seg0, L.nseg, L.total, nsplit, (const cx<TI>*)inA,
+                               (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else if (MT <= 32 && variant == 0) {
-            hipLaunchKernelGGL((crs::k_elim_w<T, MT <= 32 ? MT : 32>), dim3((unsigned)L.total), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
-                               (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_elim_w<T, MT <= 32 ? MT : 32, TI>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
+                               (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else if constexpr (MT <= 32) { // blocks above 32 run the tiled kernels
             constexpr int PW = sizeof(T) == 8 ? 32 : 64;
-            hipLaunchKernelGGL((crs::k_elim<T, MT, kNT, PW>), dim3(grid_of(L.total)), dim3(kNT), 0,
-                               st, segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
-                               (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_elim<T, MT, kNT, PW, TI>), dim3(grid_of(L.total)), dim3(kNT), 0,
+                               st, segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
+                               (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
         }
     }
     template <int MT>
@@ -277,31 +282,33 @@ struct Disp {
                        int variant)
     {
         if ((MT == 16 || MT == 32) && variant == 0) {
-            hipLaunchKernelGGL((crs::k_reduce_m<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
-                               (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_reduce_m<T, (MT == 16 || MT == 32) ? MT : 16, TI>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
+                               (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else if (MT == 64) {
-            hipLaunchKernelGGL((crs::k_reduce_t<T, 64>), dim3((unsigned)L.total), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
-                               (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_reduce_t<T, 64, TI>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
+                               (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
         } else {
-            hipLaunchKernelGGL((crs::k_reduce<T, MT, kNT>), dim3(grid_of(L.total)), dim3(kNT), 0,
-                               st, segs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
-                               (const cx<T>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_reduce<T, MT, kNT, TI>), dim3(grid_of(L.total)), dim3(kNT), 0,
+                               st, segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
+                               (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
         }
     }
     template <int MT>
     static void back(const Launch& L, const Seg* segs, const void* W, void* X,
-                     const unsigned long long* flags, hipStream_t st, int variant)
+                     const unsigned long long* flags, hipStream_t st, int variant, void* U,
+                     int upd)
     {
         if ((MT == 16 || MT == 32) && variant == 0) {
             hipLaunchKernelGGL((crs::k_back_mf<T, (MT == 16 || MT == 32) ? MT : 16>), dim3((unsigned)L.total), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags);
+                               segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X, flags,
+                               (cx<double>*)U, upd);
         } else if constexpr (MT <= 32) { // blocks above 32 run the tiled kernels
             constexpr int PW = 32;
             hipLaunchKernelGGL((crs::k_back<T, MT, kNT, PW>), dim3(grid_of(L.total)), dim3(kNT), 0,
                                st, segs + L.seg0, L.nseg, L.total, (const cx<T>*)W, (cx<T>*)X,
-                               flags);
+                               flags, (cx<double>*)U, upd);
         }
     }
     template <int MT>
@@ -388,7 +395,7 @@ constexpr int64_t kTailBlocks = 1024;
 
 bool mf_class(int cls) { return cls == 2 || cls == 3; }
 
-template <class T>
+template <class T, class TI>
 void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const void* y, int mat,
               int rhs)
 {
@@ -403,12 +410,12 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
             // eight waves instead of four
             const unsigned nthr = L.total <= kPotrfWideBlocks ? 512 : 256;
             if (L.cls == kBig)
-                hipLaunchKernelGGL((crs::k_potrf_big<T, false>), dim3((unsigned)L.total), dim3(nthr), 0,
-                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                hipLaunchKernelGGL((crs::k_potrf_big<T, false, TI>), dim3((unsigned)L.total), dim3(nthr), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
                                    (cx<T>*)c.ws, c.flags);
             else
-                hipLaunchKernelGGL((crs::k_potrf_big<T, true>), dim3((unsigned)L.total), dim3(nthr), 0,
-                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const cx<T>*)inA,
+                hipLaunchKernelGGL((crs::k_potrf_big<T, true, TI>), dim3((unsigned)L.total), dim3(nthr), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
                                    (cx<T>*)c.ws, c.flags);
         }
         const int ns = (mat ? 2 * b.S : 0) + (rhs ? b.K16 : 0);
@@ -417,13 +424,13 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
             const int ngrp = (ns + NC - 1) / NC;
             Timed tm(c.p, KID_TRSM, c.st, L.cls, L.f64);
             if (sizeof(T) == 8 && L.total >= kTrsmStripBlocks)
-                hipLaunchKernelGGL((crs::k_trsm_strip<T>), dim3(grid8(L.total * ns)), dim3(64), 0,
+                hipLaunchKernelGGL((crs::k_trsm_strip<T, TI>), dim3(grid8(L.total * ns)), dim3(64), 0,
                                    c.st, c.dsegs + L.seg0, L.nseg, L.total, ns, mat, rhs,
-                                   (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+                                   (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
             else
-                hipLaunchKernelGGL((crs::k_trsm_big<T>), dim3(grid8(L.total * ngrp)), dim3(64 * b.S),
+                hipLaunchKernelGGL((crs::k_trsm_big<T, TI>), dim3(grid8(L.total * ngrp)), dim3(64 * b.S),
                                    0, c.st, c.dsegs + L.seg0, L.nseg, L.total, ngrp, mat, rhs,
-                                   (const cx<T>*)inB, (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+                                   (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
         }
         return;
     }
@@ -435,12 +442,12 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
         const int nst = (mat ? 2 * b.S : 0) + (rhs ? b.K16 : 0);
         nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nst, kTailWaves / L.total));
     }
-#define CALL(MT) Disp<T>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st, v, nsplit)
+#define CALL(MT) Disp<T, TI>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st, v, nsplit)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
 
-template <class T>
+template <class T, class TI>
 void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int mat, int rhs)
 {
     const void* inA = L.userAB ? A : c.ws;
@@ -455,8 +462,8 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
         const bool staged = mat && L.cls == kBig;
         if (staged) {
             const int T64 = (b.S + 3) / 4, nm = T64 * (T64 + 1) / 2 + T64 * T64;
-            hipLaunchKernelGGL((crs::k_reduce_lds<T>), dim3(grid8(L.total * nm)), dim3(256), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nm, (const cx<T>*)inA,
+            hipLaunchKernelGGL((crs::k_reduce_lds<T, TI>), dim3(grid8(L.total * nm)), dim3(256), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nm, (const cx<TI>*)inA,
                                (cx<T>*)c.ws, c.flags);
         }
         const int mt = mat && !staged ? 1 : 0;
@@ -464,55 +471,58 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
             // 32 < m <= 64: one wave per 16 x 16 tile (four times the waves of
             // the 32 x 32 tiles for these short contractions)
             const int nt = b.S * (b.S + 1) / 2 + b.S * b.S + (rhs ? b.S * b.K16 : 0);
-            hipLaunchKernelGGL((crs::k_reduce_big<T, 1>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nt, 1, rhs, (const cx<T>*)inA,
-                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 1, TI>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, 1, rhs, (const cx<TI>*)inA,
+                               (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
             return;
         }
         if (!mt && rhs && b.K16 == 1) {
             // y' alone with at most 16 columns: 16 x 16 tiles waste half as
             // many MFMA columns as 32 x 32 ones
             const int nt = b.S;
-            hipLaunchKernelGGL((crs::k_reduce_big<T, 1>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nt, 0, rhs, (const cx<T>*)inA,
-                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 1, TI>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, 0, rhs, (const cx<TI>*)inA,
+                               (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
             return;
         }
         const int nt = (mt ? b.T32 * (b.T32 + 1) / 2 + b.T32 * b.T32 : 0) + (rhs ? b.T32 * b.K32 : 0);
         if (nt > 0)
-            hipLaunchKernelGGL((crs::k_reduce_big<T, 2>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nt, mt, rhs, (const cx<T>*)inA,
-                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 2, TI>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, mt, rhs, (const cx<TI>*)inA,
+                               (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
         return;
     }
     if (mf_class(L.cls) && L.total <= kTailBlocks) {
         const BigDims b = big_dims(c.p, L);
         const int nt = (mat ? b.S * (b.S + 1) / 2 + b.S * b.S : 0) + (rhs ? b.S * b.K16 : 0);
         if (nt > 0)
-            hipLaunchKernelGGL((crs::k_reduce_big<T, 1>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nt, mat, rhs, (const cx<T>*)inA,
-                               (const cx<T>*)iny, (cx<T>*)c.ws, c.flags);
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 1, TI>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, mat, rhs, (const cx<TI>*)inA,
+                               (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
         return;
     }
-#define CALL(MT) Disp<T>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st, v)
+#define CALL(MT) Disp<T, TI>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st, v)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
 
+// upd (mixed form): 0 plain back substitution; 1 / 2 the level-0 launches
+// assign / add their corrections to the caller's FP64 x.
 template <class T>
-void run_back(const Ctx& c, const Launch& L, void* x)
+void run_back(const Ctx& c, const Launch& L, void* x, int upd)
 {
     void* X = L.userX ? x : c.ws;
+    const int u = L.upd ? upd : 0;
     Timed tm(c.p, KID_BACK, c.st, L.cls, L.f64);
     if (tiled(L.cls)) {
         const BigDims b = big_dims(c.p, L);
         hipLaunchKernelGGL((crs::k_back_big<T>), dim3(grid8(L.total * b.K16)), dim3(64 * b.S), 0, c.st,
                            c.dsegs + L.seg0, L.nseg, L.total, b.K16, (const cx<T>*)c.ws, (cx<T>*)X,
-                           c.flags);
+                           c.flags, (cx<double>*)x, u);
         return;
     }
     const int v = c.p->var[2][L.cls][L.f64];
-#define CALL(MT) Disp<T>::template back<MT>(L, c.dsegs, c.ws, X, c.flags, c.st, v)
+#define CALL(MT) Disp<T>::template back<MT>(L, c.dsegs, c.ws, X, c.flags, c.st, v, x, u)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
@@ -600,7 +610,7 @@ void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count cou
     for (int lvl = 0; lvl < nlev; ++lvl)
         for (int f = 0; f < 2; ++f)
             for (int c = 0; c < kNumCls; ++c) {
-                Launch L{lvl, c, f, (int)p->segs.size(), 0, 0, false, false, false};
+                Launch L{lvl, c, f, (int)p->segs.size(), 0, 0, false, false, false, false, false};
                 for (int s = 0; s < p->batch; ++s) {
                     if (p->cls[s] != c || lvl >= (int)p->lv[s].size())
                         continue;
@@ -622,6 +632,7 @@ void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count cou
                     g.oA = v.oA; g.oB = v.oB; g.oy = v.oy;
                     g.ox = v.ox; g.xo = v.xo; g.xs = v.xs;
                     g.oD = v.oD;
+                    g.oU = v.oU;
                     if (p->sched == CRSOLVE_SCHED_CR) {
                         g.d = 1;
                         g.e0 = 0; g.es = 2; g.ne = v.ne;
@@ -642,6 +653,8 @@ void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count cou
                     L.userAB = v.userAB;
                     L.userY = v.userY;
                     L.userX = v.userX;
+                    L.in64 = v.in64;
+                    L.upd = v.upd;
                     p->segs.push_back(g);
                     ++L.nseg;
                 }
@@ -687,16 +700,16 @@ int build_plan(crsolve_plan* p)
     const size_t e32 = sizeof(cx<float>), e64 = sizeof(cx<double>);
 
     // residual norm partials and totals (FP64 inputs); for refinement also
-    // the correction d (complex FP32, laid out like y) and the info table
-    std::vector<int64_t> oA32(p->batch, 0), oB32(p->batch, 0), or32(p->batch, 0),
-        or64(p->batch, 0), oxt(p->batch, 0);
+    // the correction d (complex FP32, laid out like y), the residual r
+    // (complex FP64, laid out like y), the info table and the fallback bits
+    std::vector<int64_t> oxt(p->batch, 0);
     const bool io64 = refine || f64native;
     if (io64) {
         p->off_part = a.off;
-        // one pair of partial sums per (block row, 16-row tile)
+        // one pair of partial sums per residual work item
         int64_t nparts = 0;
         for (int s = 0; s < p->batch; ++s)
-            nparts += (int64_t)p->N[s] * ((p->m[s] + 15) / 16);
+            nparts += (int64_t)p->N[s] * crs::resid_items(p->m[s], p->k[s]);
         a.off = align_up(a.off + sizeof(double) * 2 * (size_t)std::max<int64_t>(nparts, 1));
         p->off_norms = a.off;
         a.off = align_up(a.off + sizeof(double) * 2 * p->batch);
@@ -704,6 +717,8 @@ int build_plan(crsolve_plan* p)
     if (refine) {
         p->off_d32 = a.off;
         a.off = align_up(a.off + (size_t)p->toty * e32);
+        p->off_r64 = a.off;
+        a.off = align_up(a.off + (size_t)p->toty * e64);
         p->off_info = a.off;
         a.off = align_up(a.off + sizeof(double) * 2 * p->batch);
         p->off_fbits = a.off;
@@ -750,30 +765,18 @@ int build_plan(crsolve_plan* p)
                 v.og = a.take(v.ne * mk, es);
                 v.oyo = a.take(v.nk * mk, es);
             }
-            // level inputs
+            // level inputs: level 0 reads the caller's arrays (the mixed
+            // form's right-hand side is y in the first pass and the FP64
+            // residual, laid out like y, in the corrections; its FP32 level 0
+            // rounds the FP64 inputs on load)
             for (size_t l = 0; l < L.size(); ++l) {
                 LevelSpec& v = L[l];
+                v.in64 = v.f64 || (refine && l == 0);
                 if (l == 0) {
-                    if (!refine || v.f64) {
-                        v.userAB = true;
-                        v.oA = p->offA[s];
-                        v.oB = p->offB[s];
-                    } else {
-                        oA32[s] = a.take((int64_t)p->N[s] * mm, e32);
-                        oB32[s] = a.take((int64_t)(p->N[s] - 1) * mm, e32);
-                        v.oA = oA32[s];
-                        v.oB = oB32[s];
-                    }
-                    if (!refine) {
-                        v.userY = true;
-                        v.oy = p->offy[s];
-                    } else if (v.f64) {
-                        or64[s] = a.take((int64_t)p->N[s] * mk, e64);
-                        v.oy = or64[s];
-                    } else {
-                        or32[s] = a.take((int64_t)p->N[s] * mk, e32);
-                        v.oy = or32[s];
-                    }
+                    v.userAB = v.userY = true;
+                    v.oA = p->offA[s];
+                    v.oB = p->offB[s];
+                    v.oy = p->offy[s];
                 } else if ((int)l == sw) {
                     // first FP64 level: its inputs are FP64 copies of the
                     // previous (FP32) level's reduced system
@@ -791,6 +794,11 @@ int build_plan(crsolve_plan* p)
                 oxt[s] = a.take((int64_t)L[sw].n * mk, e64);
             for (size_t l = 0; l < L.size(); ++l) {
                 LevelSpec& v = L[l];
+                if (refine && l == 0) {
+                    // the corrections of level 0 go straight into the FP64 x
+                    v.upd = true;
+                    v.oU = p->offy[s];
+                }
                 if (!refine) {
                     v.userX = true;
                     v.ox = p->offy[s];
@@ -863,7 +871,7 @@ int build_plan(crsolve_plan* p)
     // row, 16-row tile)
     std::vector<int64_t> rowbase(p->batch, 0);
     for (int s = 1; s < p->batch; ++s)
-        rowbase[s] = rowbase[s - 1] + (int64_t)p->N[s - 1] * ((p->m[s - 1] + 15) / 16);
+        rowbase[s] = rowbase[s - 1] + (int64_t)p->N[s - 1] * crs::resid_items(p->m[s - 1], p->k[s - 1]);
     auto sys_seg = [&](int s) {
         Seg g;
         std::memset(&g, 0, sizeof(g));
@@ -888,18 +896,18 @@ int build_plan(crsolve_plan* p)
                     continue;
                 if (kind == 1 && !io64)
                     continue;
-                Launch L{0, c, f, (int)p->segs.size(), 0, 0, false, false, false};
+                Launch L{0, c, f, (int)p->segs.size(), 0, 0, false, false, false, false, false};
                 for (int s = 0; s < p->batch; ++s) {
                     if (p->cls[s] != c || (f == 1) != (p->lv[s][0].f64 == 1))
                         continue;
                     Seg g = sys_seg(s);
-                    if (refine)
-                        g.og = p->lv[s][0].oy; // r lands where level 0 reads its rhs
+                    if (refine) // r lands in the FP64 residual buffer, laid out like y
+                        g.og = (int64_t)(p->off_r64 / e64) + p->offy[s];
                     g.w0 = L.total;
-                    // gradients: one work item per block row; residuals: one
-                    // per (block row, 16-row tile)
+                    // gradients: one work item per block row; residuals:
+                    // resid_items per block row
                     L.total += kind == 0 ? (int64_t)p->N[s]
-                                         : (int64_t)p->N[s] * ((p->m[s] + 15) / 16);
+                                         : (int64_t)p->N[s] * crs::resid_items(p->m[s], p->k[s]);
                     p->segs.push_back(g);
                     ++L.nseg;
                 }
@@ -913,27 +921,10 @@ int build_plan(crsolve_plan* p)
         p->segs.push_back(sys_seg(s));
 
     // conversion jobs (refine)
-    p->cvt_factor0.clear();
-    p->cvt_solve0.clear();
     p->cvt_factor_sw.assign(maxlev + 1, {});
     p->cvt_solve_sw.assign(maxlev + 1, {});
     p->scatter_sw.assign(maxlev + 1, {});
     if (refine) {
-        std::vector<JobIn> jA, jB, jy32, jy64;
-        for (int s = 0; s < p->batch; ++s) {
-            const int64_t mm = (int64_t)p->m[s] * p->m[s], mk = (int64_t)p->m[s] * p->k[s];
-            if (!p->lv[s][0].f64) {
-                jA.push_back({p->offA[s], oA32[s], (int64_t)p->N[s] * mm});
-                jB.push_back({p->offB[s], oB32[s], (int64_t)(p->N[s] - 1) * mm});
-                jy32.push_back({p->offy[s], or32[s], (int64_t)p->N[s] * mk});
-            } else {
-                jy64.push_back({p->offy[s], or64[s], (int64_t)p->N[s] * mk});
-            }
-        }
-        add_cvt(p, p->cvt_factor0, jA, 1, 0, true, 0);
-        add_cvt(p, p->cvt_factor0, jB, 1, 0, true, 1);
-        add_cvt(p, p->cvt_solve0, jy32, 1, 0, true, 2);
-        add_cvt(p, p->cvt_solve0, jy64, 1, 1, true, 2);
         for (int l = 1; l <= maxlev; ++l) {
             std::vector<JobIn> fa, fbv, fy;
             for (int s = 0; s < p->batch; ++s) {
@@ -951,7 +942,9 @@ int build_plan(crsolve_plan* p)
             add_cvt(p, p->cvt_factor_sw[l], fbv, 0, 1, false, 1);
             add_cvt(p, p->cvt_solve_sw[l], fy, 0, 1, false, 2);
         }
-        for (int l = 0; l <= maxlev; ++l) {
+        // level 0 of a system that is FP64 throughout moves its corrections
+        // into x itself (no scatter)
+        for (int l = 1; l <= maxlev; ++l) {
             std::vector<JobIn> sc;
             for (int s = 0; s < p->batch; ++s) {
                 if (p->sw[s] != l)
@@ -1021,16 +1014,20 @@ void levels_down(const Ctx& c, const void* A, const void* B, const void* y, int 
         for (; ie < p->elim.size() && p->elim[ie].level == l; ++ie) {
             const Launch& L = p->elim[ie];
             if (L.f64)
-                run_elim<double>(c, L, A, B, y, mat, rhs);
+                run_elim<double, double>(c, L, A, B, y, mat, rhs);
+            else if (L.in64)
+                run_elim<float, double>(c, L, A, B, y, mat, rhs);
             else
-                run_elim<float>(c, L, A, B, y, mat, rhs);
+                run_elim<float, float>(c, L, A, B, y, mat, rhs);
         }
         for (; ir < p->reduce.size() && p->reduce[ir].level == l; ++ir) {
             const Launch& L = p->reduce[ir];
             if (L.f64)
-                run_reduce<double>(c, L, A, y, mat, rhs);
+                run_reduce<double, double>(c, L, A, y, mat, rhs);
+            else if (L.in64)
+                run_reduce<float, double>(c, L, A, y, mat, rhs);
             else
-                run_reduce<float>(c, L, A, y, mat, rhs);
+                run_reduce<float, float>(c, L, A, y, mat, rhs);
         }
         if (l + 1 < (int)p->cvt_factor_sw.size()) {
             if (mat)
@@ -1045,8 +1042,8 @@ void levels_down(const Ctx& c, const void* A, const void* B, const void* y, int 
 
 // All levels upwards.  Before the back substitution of level l (FP32), the
 // unknowns of systems whose FP64 tail starts at level l + 1 move into the
-// FP32 correction; systems that are FP64 from level 0 move theirs last.
-void levels_up(const Ctx& c, void* x)
+// FP32 correction.  upd: see run_back.
+void levels_up(const Ctx& c, void* x, int upd = 0)
 {
     const crsolve_plan* p = c.p;
     const int nsc = (int)p->scatter_sw.size();
@@ -1058,9 +1055,9 @@ void levels_up(const Ctx& c, void* x)
                 for (const CvtLaunch& cl : p->scatter_sw[next - 1])
                     run_cvt(c, cl, nullptr, nullptr, nullptr);
         if (L.f64)
-            run_back<double>(c, L, x);
+            run_back<double>(c, L, x, upd);
         else
-            run_back<float>(c, L, x);
+            run_back<float>(c, L, x, upd);
     }
     for (; next > 0; --next)
         if (next - 1 < nsc)
@@ -1091,25 +1088,27 @@ void residual(const Ctx& c, const void* A, const void* B, const void* x, const v
 {
     const crsolve_plan* p = c.p;
     double* part = (double*)(c.ws + p->off_part);
-    void* R = store_r ? (void*)c.ws : nullptr;
+    cx<double>* R = store_r ? (cx<double>*)c.ws : nullptr;
     for (const Launch& L : p->resid) {
         Timed tm(p, KID_RESIDUAL, c.st);
-        hipLaunchKernelGGL(crs::k_residual, dim3(grid8(L.total)), dim3(64), 0, c.st,
-                           c.dsegs + L.seg0, L.nseg, L.total, (const cx<double>*)A, (const cx<double>*)B,
-                           (const cx<double>*)x, (const cx<double>*)y, R, L.f64 ? 0 : 1, part);
+        // row tiles per wave: one up to m = 16, two up to 32, then groups of four
+        const auto* Ad = (const cx<double>*)A;
+        const auto* Bd = (const cx<double>*)B;
+        const auto* Xd = (const cx<double>*)x;
+        const auto* Yd = (const cx<double>*)y;
+        if (L.cls <= 2)
+            hipLaunchKernelGGL(crs::k_residual<1>, dim3(grid8(L.total)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, Ad, Bd, Xd, Yd, R, part);
+        else if (L.cls == 3)
+            hipLaunchKernelGGL(crs::k_residual<2>, dim3(grid8(L.total)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, Ad, Bd, Xd, Yd, R, part);
+        else
+            hipLaunchKernelGGL(crs::k_residual<4>, dim3(grid8(L.total)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, Ad, Bd, Xd, Yd, R, part);
     }
     Timed tm(p, KID_NORMS, c.st);
     hipLaunchKernelGGL(crs::k_norms, dim3(p->batch), dim3(256), 0, c.st, c.dsegs + p->norm_seg0,
                        p->batch, (const double*)part, (double*)(c.ws + p->off_norms));
-}
-
-void update(const Ctx& c, void* x, int assign)
-{
-    const crsolve_plan* p = c.p;
-    Timed tm(p, KID_UPDATE, c.st);
-    const unsigned g = (unsigned)std::min<int64_t>((p->toty + 255) / 256, 1 << 16);
-    hipLaunchKernelGGL(crs::k_update, dim3(g), dim3(256), 0, c.st, (cx<double>*)x,
-                       (const cx<float>*)(c.ws + p->off_d32), p->toty, assign);
 }
 
 int read_norms(const Ctx& c, std::vector<double>& h)
@@ -1198,39 +1197,31 @@ void enqueue_native_fs(const Ctx& c, const void* A, const void* B, const void* y
 
 void enqueue_refine_factor(const Ctx& c, const void* A, const void* B)
 {
-    for (const CvtLaunch& cl : c.p->cvt_factor0)
-        run_cvt(c, cl, A, B, nullptr);
     init_flags(c);
     levels_down(c, A, B, nullptr, 1, 0);
 }
 
 // One solve pass of the mixed form: d = A^{-1} r with the mixed factors
-// (first pass: r = y), x = d or x += d, then the FP64 residual and its norms.
+// (first pass: r = y, read from the caller's y; later passes: the FP64
+// residual), x = d or x += d inside the level-0 back substitution, then the
+// FP64 residual and its norms.
 void enqueue_refine_pass(const Ctx& c, const void* A, const void* B, const void* y, void* x,
                          bool first)
 {
-    if (first)
-        for (const CvtLaunch& cl : c.p->cvt_solve0)
-            run_cvt(c, cl, nullptr, nullptr, y);
-    levels_down(c, nullptr, nullptr, nullptr, 0, 1);
-    levels_up(c, x);
-    update(c, x, first ? 1 : 0);
+    levels_down(c, nullptr, nullptr, first ? y : (const void*)(c.ws + c.p->off_r64), 0, 1);
+    levels_up(c, x, first ? 1 : 2);
     residual(c, A, B, x, y, true);
 }
 
-// The factorization fused with the first solve pass of the mixed form:
-// conversions, all levels down with matrix and right-hand side together, back
-// substitution, x = d, then the FP64 residual and its norms.
+// The factorization fused with the first solve pass of the mixed form: all
+// levels down with matrix and right-hand side together (level 0 reads the
+// caller's FP64 A, B, y), back substitution with x = d at level 0, then the
+// FP64 residual and its norms.
 void enqueue_refine_fused(const Ctx& c, const void* A, const void* B, const void* y, void* x)
 {
-    for (const CvtLaunch& cl : c.p->cvt_factor0)
-        run_cvt(c, cl, A, B, nullptr);
-    for (const CvtLaunch& cl : c.p->cvt_solve0)
-        run_cvt(c, cl, nullptr, nullptr, y);
     init_flags(c);
-    levels_down(c, A, B, nullptr, 1, 1);
-    levels_up(c, x);
-    update(c, x, 1);
+    levels_down(c, A, B, y, 1, 1);
+    levels_up(c, x, 1);
     residual(c, A, B, x, y, true);
 }
 

@@ -37,6 +37,14 @@ struct alignas(2 * sizeof(T)) cx {
     T r, i;
 };
 
+// Element of a level input read in another precision (the mixed form's FP32
+// levels read the caller's FP64 arrays at level 0 and round on load).
+template <class T, class S>
+__device__ __forceinline__ cx<T> cvt(const cx<S> v)
+{
+    return cx<T>{(T)v.r, (T)v.i};
+}
+
 // c -= a * b
 template <class T>
 __device__ __forceinline__ void msub(cx<T>& c, const cx<T> a, const cx<T> b)
@@ -83,7 +91,39 @@ struct Seg {
     int64_t oAo, oBo, oyo;    // reduced system
     int64_t ox;               // unknowns of the system
     int64_t oD;               // inverse diagonal tiles (block sizes above 32)
+    int64_t oU;               // mixed form, level 0: the system's FP64 solution
 };
+
+// Store of element e of the unknowns x_p of an eliminated block.  Normally
+// into xp (the level's unknowns); in the mixed form's level 0 (upd != 0) the
+// value is the correction d_p and goes into the FP64 solution u_p instead:
+// u = d (upd = 1) or u += d (upd = 2).
+template <class T>
+__device__ __forceinline__ void put_x(cx<T>* xp, cx<double>* up, int upd, int64_t e, cx<T> v)
+{
+    if (!upd) {
+        xp[e] = v;
+    } else if (upd == 1) {
+        up[e] = cvt<double>(v);
+    } else {
+        cx<double> o = up[e];
+        o.r += (double)v.r;
+        o.i += (double)v.i;
+        up[e] = o;
+    }
+}
+
+// The mixed form's level 0 also moves the correction of the kept neighbour
+// q = p + d (solved at the deeper levels) into the FP64 solution: elements
+// [e0, e1) with stride es of u_q (+)= d_q.  Every kept block of level 0 has
+// exactly one eliminated left neighbour, so each is updated once.
+template <class T>
+__device__ __forceinline__ void put_kept(const cx<T>* dq, cx<double>* uq, int upd, int64_t e0,
+                                         int64_t e1, int64_t es)
+{
+    for (int64_t e = e0; e < e1; e += es)
+        put_x<T>(nullptr, uq, upd, e, dq[e]);
+}
 
 constexpr unsigned long long kNoFail = ~0ull;
 
@@ -118,11 +158,11 @@ __device__ __forceinline__ int find_seg(const Seg* __restrict__ s, int nseg, int
 
 // ----------------------------------------------------------------- k_elim
 
-template <class T, int MT, int NT, int PW>
+template <class T, int MT, int NT, int PW, class TI = T>
 __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int nseg, int64_t total,
-                                             const cx<T>* __restrict__ inA,
-                                             const cx<T>* __restrict__ inB,
-                                             const cx<T>* __restrict__ iny, cx<T>* __restrict__ W,
+                                             const cx<TI>* __restrict__ inA,
+                                             const cx<TI>* __restrict__ inB,
+                                             const cx<TI>* __restrict__ iny, cx<T>* __restrict__ W,
                                              unsigned long long* __restrict__ flags, int with_mat,
                                              int with_rhs)
 {
@@ -145,9 +185,9 @@ __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int n
         cx<T>* Lg = W + s.oL + t * (int64_t)m * m;
         __syncthreads();
         if (with_mat) {
-            const cx<T>* Ap = inA + s.oA + (int64_t)p * m * m;
+            const cx<TI>* Ap = inA + s.oA + (int64_t)p * m * m;
             for (int e = tid; e < m * m; e += NT)
-                sL[(e / m) * LD + e % m] = Ap[e];
+                sL[(e / m) * LD + e % m] = cvt<T>(Ap[e]);
             if (tid == 0)
                 sFail = 0;
             __syncthreads();
@@ -198,7 +238,7 @@ __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int n
         // forward substitution on the operands of Eq. (Formulas)
         for (int src = 0; src < 3; ++src) {
             int ncol, ldg;
-            const cx<T>* G;
+            const cx<TI>* G;
             cx<T>* out;
             bool herm = false;
             if (src == 0) {
@@ -230,14 +270,14 @@ __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int n
                 if (herm) {
                     for (int e = tid; e < m * cw; e += NT) {
                         const int c = e / m, r = e % m;
-                        cx<T> v = G[(int64_t)(c0 + c) * m + r];
+                        cx<T> v = cvt<T>(G[(int64_t)(c0 + c) * m + r]);
                         v.i = -v.i;
                         sG[r * GLD + c] = v;
                     }
                 } else {
                     for (int e = tid; e < m * cw; e += NT) {
                         const int r = e / cw, c = e % cw;
-                        sG[r * GLD + c] = G[(int64_t)r * ldg + c0 + c];
+                        sG[r * GLD + c] = cvt<T>(G[(int64_t)r * ldg + c0 + c]);
                     }
                 }
                 __syncthreads();
@@ -310,10 +350,10 @@ __device__ __forceinline__ void gram_sub(cx<T> (&acc)[R][R], const cx<T>* __rest
     }
 }
 
-template <class T, int MT, int NT>
+template <class T, int MT, int NT, class TI = T>
 __global__ __launch_bounds__(NT) void k_reduce(const Seg* __restrict__ segs, int nseg, int64_t total,
-                                               const cx<T>* __restrict__ inA,
-                                               const cx<T>* __restrict__ iny,
+                                               const cx<TI>* __restrict__ inA,
+                                               const cx<TI>* __restrict__ iny,
                                                cx<T>* __restrict__ W,
                                                const unsigned long long* __restrict__ flags,
                                                int with_mat, int with_rhs)
@@ -340,13 +380,13 @@ __global__ __launch_bounds__(NT) void k_reduce(const Seg* __restrict__ segs, int
             continue; // the level's elimination broke down: stop this system
         if (with_mat) {
             cx<T> acc[R][R];
-            const cx<T>* Aq = inA + s.oA + q * mm;
+            const cx<TI>* Aq = inA + s.oA + q * mm;
 #pragma unroll
             for (int i = 0; i < R; ++i)
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     const int a = ty + 16 * i, b = tx + 16 * j;
-                    acc[i][j] = (a < m && b < m && b <= a) ? Aq[a * m + b] : cx<T>{T(0), T(0)};
+                    acc[i][j] = (a < m && b < m && b <= a) ? cvt<T>(Aq[a * m + b]) : cx<T>{T(0), T(0)};
                 }
             if (hasL) {
                 const cx<T>* P = W + s.oP + tl * mm;
@@ -389,7 +429,7 @@ __global__ __launch_bounds__(NT) void k_reduce(const Seg* __restrict__ segs, int
             }
         }
         if (with_rhs) {
-            const cx<T>* yq = iny + s.oy + q * mk;
+            const cx<TI>* yq = iny + s.oy + q * mk;
             cx<T>* yo = W + s.oyo + oi * mk;
             for (int c0 = 0; c0 < k; c0 += 16 * R) {
                 const int cw = min(16 * R, k - c0);
@@ -399,7 +439,7 @@ __global__ __launch_bounds__(NT) void k_reduce(const Seg* __restrict__ segs, int
 #pragma unroll
                     for (int j = 0; j < R; ++j) {
                         const int a = ty + 16 * i, b = tx + 16 * j;
-                        acc[i][j] = (a < m && b < cw) ? yq[a * k + c0 + b] : cx<T>{T(0), T(0)};
+                        acc[i][j] = (a < m && b < cw) ? cvt<T>(yq[a * k + c0 + b]) : cx<T>{T(0), T(0)};
                     }
                 if (hasL)
                     gram_sub<T, R, NT, KC>(acc, W + s.oP + tl * mm, m, m, W + s.og + tl * mk + c0,
@@ -425,7 +465,8 @@ __global__ __launch_bounds__(NT) void k_reduce(const Seg* __restrict__ segs, int
 template <class T, int MT, int NT, int PW>
 __global__ __launch_bounds__(NT) void k_back(const Seg* __restrict__ segs, int nseg, int64_t total,
                                              const cx<T>* __restrict__ W, cx<T>* __restrict__ X,
-                                             const unsigned long long* __restrict__ flags)
+                                             const unsigned long long* __restrict__ flags,
+                                             cx<double>* __restrict__ U, int upd)
 {
     constexpr int LD = MT + 1;
     constexpr int GLD = PW + 1;
@@ -443,14 +484,20 @@ __global__ __launch_bounds__(NT) void k_back(const Seg* __restrict__ segs, int n
         const bool failed = flags[s.sys] != kNoFail;
         const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
         cx<T>* xp = X + s.ox + (s.xo + s.xs * p) * mk;
+        cx<double>* up = upd ? U + s.oU + p * mk : nullptr;
         if (failed) {
             const T nan = T(NAN);
-            for (int e = tid; e < m * k; e += NT)
-                xp[e] = cx<T>{nan, nan};
+            for (int e = tid; e < m * k; e += NT) {
+                put_x<T>(xp, up, upd ? 1 : 0, e, cx<T>{nan, nan});
+                if (upd && hasNext)
+                    put_x<T>(xp, up + d * mk, 1, e, cx<T>{nan, nan});
+            }
             continue;
         }
         const cx<T>* xm = X + s.ox + (s.xo + s.xs * (p - d)) * mk;
         const cx<T>* xn = X + s.ox + (s.xo + s.xs * (p + d)) * mk;
+        if (upd && hasNext)
+            put_kept<T>(xn, up + d * mk, upd, tid, m * k, NT);
         const cx<T>* L = W + s.oL + t * mm;
         const cx<T>* P = W + s.oP + t * mm;
         const cx<T>* Q = W + s.oQ + t * mm;
@@ -498,7 +545,7 @@ __global__ __launch_bounds__(NT) void k_back(const Seg* __restrict__ segs, int n
             }
             for (int e = tid; e < m * cw; e += NT) {
                 const int r = e / cw, c = e % cw;
-                xp[r * k + c0 + c] = sW[r * GLD + c];
+                put_x<T>(xp, up, upd, r * k + c0 + c, sW[r * GLD + c]);
             }
         }
     }

@@ -295,9 +295,9 @@ __device__ __forceinline__ void wave_lds_sync()
 // three waves per SIMD; otherwise the rows go through LDS and the compiler
 // keeps two waves per SIMD.  The first is faster at m <= 64 (the diagonal
 // tiles are a larger share of the work), the second at m = 256.
-template <class T, bool RB>
+template <class T, bool RB, class TI = T>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2, 8))) void k_potrf_big(const Seg* __restrict__ segs, int nseg,
-                                                   int64_t total, const cx<T>* __restrict__ inA,
+                                                   int64_t total, const cx<TI>* __restrict__ inA,
                                                    cx<T>* __restrict__ W,
                                                    unsigned long long* __restrict__ flags)
 {
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2,
     if ((flags[s.sys] >> 40) < (unsigned long long)s.level)
         return; // broke down at an earlier level
     const int64_t mm = (int64_t)m * m;
-    const cx<T>* Ap = inA + s.oA + (int64_t)p * mm;
+    const cx<TI>* Ap = inA + s.oA + (int64_t)p * mm;
     cx<T>* Lg = W + s.oL + t * mm;
     cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
     if (tid == 0)
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2,
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * R + MF<T>::row(kr, v), j = c0 + cc;
                 if (i < m && j < m && (R > I || j <= i)) {
-                    const cx<T> a = Ap[(int64_t)i * m + j];
+                    const cx<T> a = cvt<T>(Ap[(int64_t)i * m + j]);
                     const cx<T> o{a.r - acc.re(0, 0, v), a.i - acc.im(0, 0, v)};
                     if (R == I) // the diagonal tile goes to wave 0 through LDS
                         sT[(i - c0) * 17 + (j - c0)] = o;
@@ -460,11 +460,11 @@ constexpr int trsm_strips()
 // X_J = D_J (G_J - acc_J), the accumulator being the right operand (see the
 // note in k_elim_mf), stores it and publishes it in LDS; every wave I > J
 // then accumulates acc_I += L_IJ X_J (its operand loaded one step ahead).
-template <class T>
+template <class T, class TI = T>
 __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int ngrp, int with_mat,
-                                                   int with_rhs, const cx<T>* __restrict__ inB,
-                                                   const cx<T>* __restrict__ iny,
+                                                   int with_rhs, const cx<TI>* __restrict__ inB,
+                                                   const cx<TI>* __restrict__ iny,
                                                    cx<T>* __restrict__ W,
                                                    const unsigned long long* __restrict__ flags)
 {
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs,
     // per strip slot b: element (r, c) of the right-hand side is
     // G[b][r * gr[b] + c * gc[b]] (conjugated for B_p^H), the solution goes
     // to out[b][r * ld[b] + c], columns c0[b] .. c0[b] + nc[b] - 1
-    const cx<T>* G[NC];
+    const cx<TI>* G[NC];
     cx<T>* out[NC];
     int gr[NC], gc[NC], ld[NC], c0[NC], nc[NC];
     bool cj[NC], on[NC];
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs,
             const int r = r0 + MF<T>::row(kr, v);
             cx<T> x = czero<T>();
             if (own && on[b] && r < m && cc < nc[b])
-                x = G[b][r * gr[b] + (c0[b] + cc) * gc[b]];
+                x = cvt<T>(G[b][r * gr[b] + (c0[b] + cc) * gc[b]]);
             ar[b][v] = x.r;
             ai[b][v] = cj[b] ? -x.i : x.i;
         }
@@ -620,11 +620,11 @@ __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs,
 // a block: with_mat gives 2 S strips (columns of B_p^H, then of B_{p-d}),
 // with_rhs ceil(k / 16) strips of y_p after them.  Used for FP64 levels with
 // many blocks, where the work-group form's idle waves would cost throughput.
-template <class T>
+template <class T, class TI = T>
 __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs, int nseg,
                                                  int64_t total, int nstrip, int with_mat,
-                                                 int with_rhs, const cx<T>* __restrict__ inB,
-                                                 const cx<T>* __restrict__ iny,
+                                                 int with_rhs, const cx<TI>* __restrict__ inB,
+                                                 const cx<TI>* __restrict__ iny,
                                                  cx<T>* __restrict__ W,
                                                  const unsigned long long* __restrict__ flags)
 {
@@ -661,7 +661,7 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
     }
     const int nc = min(16, (src == 2 ? k : m) - c0);
     // element (r, c) of the right-hand side is G[r * gr + c * gc]
-    const cx<T>* G;
+    const cx<TI>* G;
     int gr, gc;
     cx<T>* out;
     if (src == 0) {
@@ -698,7 +698,7 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int rr = MF<T>::row(kr, v), r = r0 + rr;
-            cx<T> g = (r < m && cc < nc) ? G[r * gr + (c0 + cc) * gc] : czero<T>();
+            cx<T> g = (r < m && cc < nc) ? cvt<T>(G[r * gr + (c0 + cc) * gc]) : czero<T>();
             if (src == 0)
                 g.i = -g.i;
             const T br = g.r - acc.re(0, 0, v), bi = g.i - acc.im(0, 0, v);
@@ -726,11 +726,11 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
 // TW = 1 the blocks of 32 < m <= 64, the right-hand sides with k <= 16 of
 // larger blocks, and the levels of m <= 32 with too few blocks to fill the
 // GPU one wave per block.
-template <class T, int TW>
+template <class T, int TW, class TI = T>
 __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int ntile, int with_mat,
-                                                   int with_rhs, const cx<T>* __restrict__ inA,
-                                                   const cx<T>* __restrict__ iny,
+                                                   int with_rhs, const cx<TI>* __restrict__ inA,
+                                                   const cx<TI>* __restrict__ iny,
                                                    cx<T>* __restrict__ W,
                                                    const unsigned long long* __restrict__ flags)
 {
@@ -791,7 +791,7 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
         if (hasR)
             wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{Qr + j0, 1, m, m - j0}, m);
-        const cx<T>* Aq = inA + s.oA + q * mm;
+        const cx<TI>* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll
         for (int a = 0; a < TW; ++a)
@@ -801,7 +801,7 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                 for (int v = 0; v < 4; ++v) {
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), j = j0 + 16 * b + cc;
                     if (i < m && j <= i) {
-                        const cx<T> x = Aq[i * m + j];
+                        const cx<T> x = cvt<T>(Aq[i * m + j]);
                         cx<T> o{x.r - acc.re(a, b, v), x.i - acc.im(a, b, v)};
                         if (i == j)
                             o.i = T(0);
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
         if (hasR)
             wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{gr + j0, 1, k, k - j0}, m);
-        const cx<T>* yq = iny + s.oy + q * mk;
+        const cx<TI>* yq = iny + s.oy + q * mk;
         cx<T>* vo = W + s.oyo + oi * mk;
 #pragma unroll
         for (int a = 0; a < TW; ++a)
@@ -841,7 +841,7 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                 for (int v = 0; v < 4; ++v) {
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), c = j0 + 16 * b + cc;
                     if (i < m && c < k) {
-                        const cx<T> x = yq[i * k + c];
+                        const cx<T> x = cvt<T>(yq[i * k + c]);
                         vo[i * k + c] = cx<T>{x.r - acc.re(a, b, v), x.i - acc.im(a, b, v)};
                     }
                 }
@@ -861,10 +861,10 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
 // buffers, one barrier per panel).  Items per kept block: the
 // NT (NT + 1) / 2 lower tiles of A', then the NT^2 tiles of B' (NT =
 // ceil(m / 64)).  The right-hand-side tiles y' run in k_reduce_big.
-template <class T>
+template <class T, class TI = T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_reduce_lds(const Seg* __restrict__ segs, int nseg,
                                                     int64_t total, int ntile,
-                                                    const cx<T>* __restrict__ inA,
+                                                    const cx<TI>* __restrict__ inA,
                                                     cx<T>* __restrict__ W,
                                                     const unsigned long long* __restrict__ flags)
 {
@@ -993,7 +993,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 #undef CRS_PANEL_STORE
     const int ib = i0 + 32 * wa, jb = j0 + 32 * wb;
     if (kind == 0) {
-        const cx<T>* Aq = inA + s.oA + q * mm;
+        const cx<TI>* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -1003,7 +1003,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                 for (int v = 0; v < 4; ++v) {
                     const int i = ib + 16 * a + MF<T>::row(kr, v), j = jb + 16 * b + cc;
                     if (i < m && j <= i) {
-                        const cx<T> x = Aq[(int64_t)i * m + j];
+                        const cx<T> x = cvt<T>(Aq[(int64_t)i * m + j]);
                         cx<T> o{x.r - acc.re(a, b, v), x.i - acc.im(a, b, v)};
                         if (i == j)
                             o.i = T(0);
@@ -1042,7 +1042,8 @@ __global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs,
                                                    int64_t total, int nstrip,
                                                    const cx<T>* __restrict__ W,
                                                    cx<T>* __restrict__ X,
-                                                   const unsigned long long* __restrict__ flags)
+                                                   const unsigned long long* __restrict__ flags,
+                                                   cx<double>* __restrict__ U, int upd)
 {
     using v4 = typename MF<T>::v4;
     __shared__ cx<T> sx[256]; // x_I, row-major 16 x 16
@@ -1063,15 +1064,28 @@ __global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs,
     const bool hasPrev = p - d >= 0, hasNext = p + d < s.n;
     const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
     cx<T>* xp = X + s.ox + (s.xo + s.xs * p) * mk;
+    cx<double>* up = upd ? U + s.oU + p * mk : nullptr;
     if (flags[s.sys] != kNoFail) {
         const T nan = T(NAN);
         for (int e = threadIdx.x; e < m * 16; e += blockDim.x)
-            if ((e & 15) < nc)
-                xp[(e >> 4) * k + c0 + (e & 15)] = cx<T>{nan, nan};
+            if ((e & 15) < nc) {
+                const int64_t o = (e >> 4) * k + c0 + (e & 15);
+                put_x<T>(xp, up, upd ? 1 : 0, o, cx<T>{nan, nan});
+                if (upd && hasNext)
+                    put_x<T>(xp, up + d * mk, 1, o, cx<T>{nan, nan});
+            }
         return;
     }
     const cx<T>* xm = X + s.ox + (s.xo + s.xs * (p - d)) * mk;
     const cx<T>* xn = X + s.ox + (s.xo + s.xs * (p + d)) * mk;
+    if (upd && hasNext) {
+        // this strip's columns of the kept neighbour's correction
+        for (int e = threadIdx.x; e < m * 16; e += blockDim.x)
+            if ((e & 15) < nc) {
+                const int64_t o = (e >> 4) * k + c0 + (e & 15);
+                put_x<T>(nullptr, up + d * mk, upd, o, xn[o]);
+            }
+    }
     const cx<T>* L = W + s.oL + t * mm;
     const cx<T>* P = W + s.oP + t * mm;
     const cx<T>* Q = W + s.oQ + t * mm;
@@ -1135,7 +1149,7 @@ __global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs,
                 const int rr = MF<T>::row(kr, v), r = r0 + rr;
                 sx[rr * 16 + cc] = cx<T>{xr[v], xi[v]};
                 if (r < m && cc < nc)
-                    xp[(int64_t)r * k + c0 + cc] = cx<T>{xr[v], xi[v]};
+                    put_x<T>(xp, up, upd, (int64_t)r * k + c0 + cc, cx<T>{xr[v], xi[v]});
             }
         }
         __syncthreads();

@@ -256,11 +256,11 @@ __device__ __forceinline__ void tile_nn3(Acc3<T, 1, 1>& acc, const cx<T>* __rest
 
 // ----------------------------------------------------------------- k_elim_w
 
-template <class T, int MT>
+template <class T, int MT, class TI = T>
 __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* __restrict__ segs, int nseg,
-                                               int64_t total, const cx<T>* __restrict__ inA,
-                                               const cx<T>* __restrict__ inB,
-                                               const cx<T>* __restrict__ iny,
+                                               int64_t total, const cx<TI>* __restrict__ inA,
+                                               const cx<TI>* __restrict__ inB,
+                                               const cx<TI>* __restrict__ iny,
                                                cx<T>* __restrict__ W,
                                                unsigned long long* __restrict__ flags,
                                                int with_mat, int with_rhs)
@@ -291,10 +291,10 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
         cx<T>* Lg = W + s.oL + t * mm;
         __syncthreads();
         if (with_mat) {
-            const cx<T>* Ap = inA + s.oA + (int64_t)p * mm;
+            const cx<TI>* Ap = inA + s.oA + (int64_t)p * mm;
             for (int e = lane; e < np; e += 64) {
                 const int r = tri_row(e), c = e - r * (r + 1) / 2;
-                sL[e] = Ap[r * m + c];
+                sL[e] = cvt<T>(Ap[r * m + c]);
             }
             __syncthreads();
             // left-looking Cholesky: lane r < m keeps row r in registers; at
@@ -358,9 +358,9 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
         const int nQ = (with_mat && hasPrev) ? m : 0;
         const int nY = with_rhs ? k : 0;
         const int ncol = nP + nQ + nY;
-        const cx<T>* Bp = inB + s.oB + (int64_t)p * mm;
-        const cx<T>* Bq = inB + s.oB + (int64_t)(p - d) * mm;
-        const cx<T>* yp = iny + s.oy + (int64_t)p * mk;
+        const cx<TI>* Bp = inB + s.oB + (int64_t)p * mm;
+        const cx<TI>* Bq = inB + s.oB + (int64_t)(p - d) * mm;
+        const cx<TI>* yp = iny + s.oy + (int64_t)p * mk;
         for (int vc0 = 0; vc0 < ncol; vc0 += 64) {
             const int vc = vc0 + lane;
             const bool act = vc < ncol;
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
                     __syncthreads();
                     for (int e = lane; e < m * CH; e += 64) {
                         const int row = e / CH, j = e % CH, c2 = ch * CH + j;
-                        sT[row * (CH + 1) + j] = c2 < m ? Bp[row * m + c2] : czero<T>();
+                        sT[row * (CH + 1) + j] = c2 < m ? cvt<T>(Bp[row * m + c2]) : czero<T>();
                     }
                     __syncthreads();
                     if (src == 0) {
@@ -395,12 +395,12 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
 #pragma unroll
                 for (int r = 0; r < MT; ++r)
                     if (r < m)
-                        x[r] = Bq[r * m + col];
+                        x[r] = cvt<T>(Bq[r * m + col]);
             } else if (act && src == 2) {
 #pragma unroll
                 for (int r = 0; r < MT; ++r)
                     if (r < m)
-                        x[r] = yp[r * k + col];
+                        x[r] = cvt<T>(yp[r * k + col]);
             }
             // forward substitution, L by broadcast from LDS; each row's sum
             // runs on four independent chains
@@ -486,12 +486,12 @@ __device__ __forceinline__ void inverse_tiles_lds(cx<T>* sL, int m)
 // no cross-wave synchronisation); wave 0 alone stores L and raises the
 // breakdown flag.  Levels with few blocks use nsplit > 1 to shorten the
 // chain of strips that one wave walks through.
-template <class T, int MT>
+template <class T, int MT, class TI = T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_elim_mf(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int nsplit,
-                                                   const cx<T>* __restrict__ inA,
-                                                   const cx<T>* __restrict__ inB,
-                                                   const cx<T>* __restrict__ iny,
+                                                   const cx<TI>* __restrict__ inA,
+                                                   const cx<TI>* __restrict__ inB,
+                                                   const cx<TI>* __restrict__ iny,
                                                    cx<T>* __restrict__ W,
                                                    unsigned long long* __restrict__ flags,
                                                    int with_mat, int with_rhs)
@@ -523,37 +523,37 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     const int nP = (with_mat && hasNext) ? S : 0;
     const int nQ = (with_mat && hasPrev) ? S : 0;
     const int nst = nP + nQ + (with_rhs ? (k + 15) / 16 : 0);
-    const cx<T>* Bp = inB + s.oB + (int64_t)p * mm;
-    const cx<T>* Bq = inB + s.oB + (int64_t)(p - d) * mm;
-    const cx<T>* yp = iny + s.oy + (int64_t)p * mk;
+    const cx<TI>* Bp = inB + s.oB + (int64_t)p * mm;
+    const cx<TI>* Bq = inB + s.oB + (int64_t)(p - d) * mm;
+    const cx<TI>* yp = iny + s.oy + (int64_t)p * mk;
     // element (r, c) of strip st's source is base[r * sr + c * sc], conjugated
     // for B_p^H
 #define CRS_LOAD_STRIP(st, g)                                                                      \
     do {                                                                                           \
         const int src_ = (st) < nP ? 0 : ((st) < nP + nQ ? 1 : 2);                                 \
         const int c_ = 16 * (src_ == 0 ? (st) : (src_ == 1 ? (st) - nP : (st) - nP - nQ)) + cc;    \
-        const cx<T>* base_ = src_ == 0 ? Bp : (src_ == 1 ? Bq : yp);                               \
+        const cx<TI>* base_ = src_ == 0 ? Bp : (src_ == 1 ? Bq : yp);                              \
         const int sr_ = src_ == 0 ? 1 : (src_ == 1 ? m : k), sc_ = src_ == 0 ? m : 1;               \
         const bool okc_ = c_ < (src_ == 2 ? k : m);                                                \
         const T cj_ = src_ == 0 ? T(-1) : T(1);                                                    \
-        const cx<T>* col_ = base_ + (okc_ ? c_ : 0) * sc_;                                         \
+        const cx<TI>* col_ = base_ + (okc_ ? c_ : 0) * sc_;                                        \
         _Pragma("unroll") for (int I_ = 0; I_ < S; ++I_)                                           \
             _Pragma("unroll") for (int v_ = 0; v_ < 4; ++v_)                                       \
             {                                                                                      \
                 const int r_ = 16 * I_ + MF<T>::row(kr, v_);                                       \
                 cx<T> x_ = czero<T>();                                                             \
                 if (okc_ && r_ < m)                                                                \
-                    x_ = col_[r_ * sr_];                                                           \
+                    x_ = cvt<T>(col_[r_ * sr_]);                                                   \
                 g[I_][v_] = cx<T>{x_.r, cj_ * x_.i};                                               \
             }                                                                                      \
     } while (0)
     cx<T> gn[S][4];
 
     if (with_mat) {
-        const cx<T>* Ap = inA + s.oA + (int64_t)p * mm;
+        const cx<TI>* Ap = inA + s.oA + (int64_t)p * mm;
         for (int e = lane; e < np; e += 64) {
             const int r = tri_row(e), c = e - r * (r + 1) / 2;
-            sL[e] = Ap[r * m + c];
+            sL[e] = cvt<T>(Ap[r * m + c]);
         }
         __syncthreads();
         // left-looking Cholesky, one row per lane: lane c holds row c of L,
@@ -765,10 +765,10 @@ __device__ __forceinline__ void mma_hn3(Acc3<T, 1, 1>& acc, const OpTile<T, KS>&
 //   y'_q = y_q - P_l^H g_l - Q_r^H g_r.
 // Each 16-column operand tile is loaded from memory once and reused by every
 // output tile that needs it (NT16 = MT / 16 tiles per m x m operand).
-template <class T, int MT>
+template <class T, int MT, class TI = T>
 __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs, int nseg,
-                                                    int64_t total, const cx<T>* __restrict__ inA,
-                                                    const cx<T>* __restrict__ iny,
+                                                    int64_t total, const cx<TI>* __restrict__ inA,
+                                                    const cx<TI>* __restrict__ iny,
                                                     cx<T>* __restrict__ W,
                                                     const unsigned long long* __restrict__ flags,
                                                     int with_mat, int with_rhs)
@@ -837,7 +837,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
         }
     }
     if (with_mat) {
-        const cx<T>* Aq = inA + s.oA + q * mm;
+        const cx<TI>* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll
         for (int i = 0, v = 0; i < NT16; ++i)
@@ -847,7 +847,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
                 for (int u = 0; u < 4; ++u) {
                     const int a = 16 * i + MF<T>::row(kr, u), b = 16 * j + cc;
                     if (a < m && b <= a) {
-                        const cx<T> x = Aq[a * m + b];
+                        const cx<T> x = cvt<T>(Aq[a * m + b]);
                         cx<T> o{x.r - av[v].re(0, 0, u), x.i - av[v].im(0, 0, u)};
                         if (a == b)
                             o.i = T(0);
@@ -856,7 +856,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
                 }
     }
     if (kc0) {
-        const cx<T>* yq = iny + s.oy + q * mk;
+        const cx<TI>* yq = iny + s.oy + q * mk;
         cx<T>* yo = W + s.oyo + oi * mk;
 #pragma unroll
         for (int i = 0; i < NT16; ++i)
@@ -864,7 +864,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
             for (int u = 0; u < 4; ++u) {
                 const int a = 16 * i + MF<T>::row(kr, u), c = cc;
                 if (a < m && c < kc0) {
-                    const cx<T> x = yq[a * k + c];
+                    const cx<T> x = cvt<T>(yq[a * k + c]);
                     yo[a * k + c] = cx<T>{x.r - ay[i].re(0, 0, u), x.i - ay[i].im(0, 0, u)};
                 }
             }
@@ -893,7 +893,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
     }
     // remaining right-hand-side chunks (k > 16)
     if (with_rhs && k > 16) {
-        const cx<T>* yq = iny + s.oy + q * mk;
+        const cx<TI>* yq = iny + s.oy + q * mk;
         cx<T>* yo = W + s.oyo + oi * mk;
         for (int c0 = 16; c0 < k; c0 += 16) {
 #pragma unroll
@@ -916,7 +916,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
                 for (int u = 0; u < 4; ++u) {
                     const int a = 16 * i + MF<T>::row(kr, u), c = c0 + cc;
                     if (a < m && c < k) {
-                        const cx<T> x = yq[a * k + c];
+                        const cx<T> x = cvt<T>(yq[a * k + c]);
                         yo[a * k + c] = cx<T>{x.r - ac.re(0, 0, u), x.i - ac.im(0, 0, u)};
                     }
                 }
@@ -927,10 +927,10 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
 
 // --------------------------------------------------------------- k_reduce_t
 
-template <class T, int MT>
+template <class T, int MT, class TI = T>
 __global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* __restrict__ segs, int nseg,
-                                                 int64_t total, const cx<T>* __restrict__ inA,
-                                                 const cx<T>* __restrict__ iny,
+                                                 int64_t total, const cx<TI>* __restrict__ inA,
+                                                 const cx<TI>* __restrict__ iny,
                                                  cx<T>* __restrict__ W,
                                                  const unsigned long long* __restrict__ flags,
                                                  int with_mat, int with_rhs)
@@ -958,7 +958,7 @@ __global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* 
         const cx<T>* Qr = W + s.oQ + tr * mm;
         const cx<T>* Pr = W + s.oP + tr * mm;
         if (with_mat) {
-            const cx<T>* Aq = inA + s.oA + q * mm;
+            const cx<TI>* Aq = inA + s.oA + q * mm;
             cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll 1
             for (int ti = 0; ti < NT16; ++ti) {
@@ -975,7 +975,7 @@ __global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* 
                     for (int v = 0; v < 4; ++v) {
                         const int i = 16 * ti + MF<T>::row(kr, v), j = 16 * tj + cc;
                         if (i < m && j <= i) {
-                            const cx<T> a = Aq[i * m + j];
+                            const cx<T> a = cvt<T>(Aq[i * m + j]);
                             cx<T> o{a.r - cr[v], a.i - ci[v]};
                             if (i == j)
                                 o.i = T(0);
@@ -1009,7 +1009,7 @@ __global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* 
         if (with_rhs) {
             const cx<T>* gl = W + s.og + tl * mk;
             const cx<T>* gr = W + s.og + tr * mk;
-            const cx<T>* yq = iny + s.oy + q * mk;
+            const cx<TI>* yq = iny + s.oy + q * mk;
             cx<T>* vo = W + s.oyo + oi * mk;
 #pragma unroll 1
             for (int ti = 0; ti < NT16; ++ti) {
@@ -1026,7 +1026,7 @@ __global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* 
                     for (int v = 0; v < 4; ++v) {
                         const int i = 16 * ti + MF<T>::row(kr, v), c = c0 + cc;
                         if (i < m && c < k) {
-                            const cx<T> a = yq[i * k + c];
+                            const cx<T> a = cvt<T>(yq[i * k + c]);
                             vo[i * k + c] = cx<T>{a.r - cr[v], a.i - ci[v]};
                         }
                     }
@@ -1047,7 +1047,8 @@ template <class T, int MT>
 __global__ __launch_bounds__(64, 2) void k_back_mf(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, const cx<T>* __restrict__ W,
                                                    cx<T>* __restrict__ X,
-                                                   const unsigned long long* __restrict__ flags)
+                                                   const unsigned long long* __restrict__ flags,
+                                                   cx<double>* __restrict__ U, int upd)
 {
     static_assert(MT == 16 || MT == 32, "one or two 16-row tiles");
     using v4 = typename MF<T>::v4;
@@ -1066,14 +1067,20 @@ __global__ __launch_bounds__(64, 2) void k_back_mf(const Seg* __restrict__ segs,
     const bool hasPrev = p - d >= 0, hasNext = p + d < s.n;
     const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
     cx<T>* xp = X + s.ox + (s.xo + s.xs * p) * mk;
+    cx<double>* up = upd ? U + s.oU + p * mk : nullptr;
     if (flags[s.sys] != kNoFail) {
         const T nan = T(NAN);
-        for (int e = lane; e < m * k; e += 64)
-            xp[e] = cx<T>{nan, nan};
+        for (int e = lane; e < m * k; e += 64) {
+            put_x<T>(xp, up, upd ? 1 : 0, e, cx<T>{nan, nan});
+            if (upd && hasNext)
+                put_x<T>(xp, up + d * mk, 1, e, cx<T>{nan, nan});
+        }
         return;
     }
     const cx<T>* xm = X + s.ox + (s.xo + s.xs * (p - d)) * mk;
     const cx<T>* xn = X + s.ox + (s.xo + s.xs * (p + d)) * mk;
+    if (upd && hasNext)
+        put_kept<T>(xn, up + d * mk, upd, lane, mk, 64);
     const cx<T>* L = W + s.oL + t * mm;
     const cx<T>* P = W + s.oP + t * mm;
     const cx<T>* Q = W + s.oQ + t * mm;
@@ -1159,9 +1166,9 @@ __global__ __launch_bounds__(64, 2) void k_back_mf(const Seg* __restrict__ segs,
             for (int v = 0; v < 4; ++v) {
                 const int r0 = MF<T>::row(kr, v);
                 if (r0 < m)
-                    xp[r0 * k + c0 + cc] = cx<T>{x0r[v], x0i[v]};
+                    put_x<T>(xp, up, upd, r0 * k + c0 + cc, cx<T>{x0r[v], x0i[v]});
                 if (S == 2 && 16 + r0 < m)
-                    xp[(16 + r0) * k + c0 + cc] = cx<T>{x1r[v], x1i[v]};
+                    put_x<T>(xp, up, upd, (16 + r0) * k + c0 + cc, cx<T>{x1r[v], x1i[v]});
             }
         }
     }

@@ -1,6 +1,7 @@
-// Kernels of the mixed-precision form: precision conversion jobs, the FP64
-// residual r = y - A x of Eq. (Axb) with deterministic per-system norms, and
-// the FP64 update x += d.
+// Kernels of the mixed-precision form: precision conversion jobs (the
+// reduced system at the first FP64 level and the FP64 tail's unknowns), and
+// the FP64 residual r = y - A x of Eq. (Axb) with deterministic per-system
+// norms.  The update x += d is part of the level-0 back substitution.
 #pragma once
 
 #include "kernels_big.hpp"
@@ -65,20 +66,91 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// One wave per (block row j, 16-row tile ti) of a system (segment n = N,
+// Work items per block row of the residual: for k = 1 one per 16-row tile
+// (VALU products), otherwise one per 16-column strip of the right-hand side,
+// with every row tile of the block row in the same wave so that x_{j-1},
+// x_j and x_{j+1} are read once per strip.
+__host__ __device__ inline int resid_items(int m, int k)
+{
+    return k == 1 ? (m + 15) >> 4 : (k + 15) >> 4;
+}
+
+// (cr, ci)[a] += H Y for the RM tiles of 16 rows at row0 + 16 a of the
+// Hermitian matrix H read from the lower triangle and the real diagonal of
+// the m x m row-major block A (H[i][t] = A[i][t] for t < i, Re A[i][i],
+// conj(A[t][i]) for t > i) and the right operand Y (as in wave_mm); the
+// contraction runs over all m columns.
+template <class T, int RM, int G>
+__device__ __forceinline__ void wave_mm_herm_r(typename MF<T>::v4 (&cr)[RM][1],
+                                               typename MF<T>::v4 (&ci)[RM][1],
+                                               const cx<T>* __restrict__ A, int m, int row0,
+                                               const WOp<T> B)
+{
+    const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+    const int ng = (m + 4 * G - 1) / (4 * G);
+    const bool ob = cc < B.no;
+    const cx<T>* pb = B.p + ((ob ? cc : 0) * B.so + kr * B.st);
+    const int sb = 4 * B.st;
+    cx<T> xa0[RM][G], yb0[G], xa1[RM][G], yb1[G];
+    auto load = [&](cx<T>(&xa)[RM][G], cx<T>(&yb)[G], int g) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int t = 4 * (g * G + u) + kr;
+#pragma unroll
+            for (int a = 0; a < RM; ++a) {
+                const int i = row0 + 16 * a + cc;
+                cx<T> v = czero<T>();
+                if (t < m && i < m) {
+                    v = A[t <= i ? i * m + t : t * m + i];
+                    v.i = t < i ? v.i : (t == i ? T(0) : -v.i);
+                }
+                xa[a][u] = v;
+            }
+            yb[u] = (t < m && ob) ? pb[(g * G + u) * sb] : czero<T>();
+        }
+    };
+    auto comp = [&](const cx<T>(&xa)[RM][G], const cx<T>(&yb)[G]) {
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+            for (int a = 0; a < RM; ++a) {
+                cr[a][0] = MF<T>::mma(xa[a][u].r, yb[u].r, cr[a][0]);
+                cr[a][0] = MF<T>::mma(-xa[a][u].i, yb[u].i, cr[a][0]);
+                ci[a][0] = MF<T>::mma(xa[a][u].r, yb[u].i, ci[a][0]);
+                ci[a][0] = MF<T>::mma(xa[a][u].i, yb[u].r, ci[a][0]);
+            }
+    };
+    load(xa0, yb0, 0);
+    for (int g = 0; g < ng; g += 2) {
+        if (g + 1 < ng)
+            load(xa1, yb1, g + 1);
+        comp(xa0, yb0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (g + 1 < ng) {
+            if (g + 2 < ng)
+                load(xa0, yb0, g + 2);
+            comp(xa1, yb1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// The FP64 residual of Eq. (Axb) for the systems of a launch (segment n = N,
 // oA/oB/ox/oy offsets into the caller's FP64 arrays, og the offset of r in
 // R, ob0 the system's first partial-sum pair):
-//   r_j = y_j - B_{j-1} x_{j-1} - A_j x_j - B_j^H x_{j+1}
-// rows 16 ti .. 16 ti + 15, stored in R (unless R is null) as FP32 (r_f32)
-// or FP64; with S = ceil(m / 16) tiles per row and it = j S + ti,
-// part[2 (ob0 + it)] = ||rows of r_j||_F^2, part[2 (ob0 + it) + 1] = the
-// same for y_j.  MFMA products, VALU products for k = 1.
+//   r_j = y_j - B_{j-1} x_{j-1} - A_j x_j - B_j^H x_{j+1},
+// stored in R (FP64, laid out like y) unless R is null.  One wave per work
+// item (resid_items per block row; it = j * items + item): for k = 1 the
+// 16-row tile `item` on VALU products, otherwise the 16-column strip `item`
+// with its RM row tiles at a time on MFMA.  part[2 (ob0 + it)] = the item's
+// ||r||_F^2, part[2 (ob0 + it) + 1] = the same for y.
+template <int RM>
 __global__ __launch_bounds__(64) void k_residual(const Seg* __restrict__ segs, int nseg,
                                                  int64_t total, const cx<double>* __restrict__ A,
                                                  const cx<double>* __restrict__ B,
                                                  const cx<double>* __restrict__ X,
                                                  const cx<double>* __restrict__ Y,
-                                                 void* __restrict__ R, int r_f32,
+                                                 cx<double>* __restrict__ R,
                                                  double* __restrict__ part)
 {
     using T = double;
@@ -89,24 +161,23 @@ __global__ __launch_bounds__(64) void k_residual(const Seg* __restrict__ segs, i
     if (w >= total)
         return;
     const Seg& s = segs[find_seg(segs, nseg, w)];
-    const int m = s.m, k = s.k, n = s.n, S = (m + 15) >> 4;
+    const int m = s.m, k = s.k, n = s.n, ni = resid_items(m, k);
     const int64_t it = w - s.w0;
-    const int j = (int)(it / S), ti = (int)(it - (int64_t)j * S);
-    const int r0 = 16 * ti;
+    const int j = (int)(it / ni), item = (int)(it - (int64_t)j * ni);
     const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
     const cx<T>* Aj = A + s.oA + j * mm;
     const cx<T>* Bm = B + s.oB + (int64_t)(j - 1) * mm;
     const cx<T>* Bj = B + s.oB + (int64_t)j * mm;
     const cx<T>* xj = X + s.ox + j * mk;
     const cx<T>* yj = Y + s.oy + j * mk;
+    cx<T>* rj = R ? R + s.og + j * mk : nullptr;
     double sr = 0.0, sy = 0.0;
     if (k == 1) {
         // one right-hand side: VALU products (an MFMA tile would use one of
         // its 16 columns).  Lane (kr, cc) sums the contraction indices
-        // t = kr, kr + 4, ... of row i = r0 + cc with the loads of the MFMA
-        // path (16 rows x 4 consecutive t per load), then the four kr lanes
-        // of a row are combined.
-        const int i = r0 + cc;
+        // t = kr, kr + 4, ... of row i = 16 item + cc (16 rows x 4
+        // consecutive t per load), then the four kr lanes of a row combine.
+        const int i = 16 * item + cc;
         const bool oi = i < m, hasM = j > 0, hasP = j + 1 < n;
         cx<T> acc = czero<T>();
 #pragma unroll 4
@@ -139,40 +210,36 @@ __global__ __launch_bounds__(64) void k_residual(const Seg* __restrict__ segs, i
             const cx<T> r{y.r - acc.r, y.i - acc.i};
             sr += r.r * r.r + r.i * r.i;
             sy += y.r * y.r + y.i * y.i;
-            if (R) {
-                if (r_f32)
-                    ((cx<float>*)R)[s.og + j * mk + i] = cx<float>{(float)r.r, (float)r.i};
-                else
-                    ((cx<double>*)R)[s.og + j * mk + i] = r;
-            }
+            if (rj)
+                rj[i] = r;
         }
-    }
-    for (int c0 = 0; c0 < k && k > 1; c0 += 16) {
-        const int cw = min(16, k - c0);
-        v4 cr[1][1], ci[1][1];
-        zero_acc<T, 1, 1>(cr, ci);
-        if (j > 0) // B_{j-1} x_{j-1}
-            wave_mm<T, 1, 1, false, false, 4>(cr, ci, WOp<T>{Bm + r0 * m, m, 1, m - r0},
-                                              WOp<T>{xj - mk + c0, 1, k, cw}, m);
-        wave_mm_herm<T, 4>(cr[0][0], ci[0][0], Aj, m, r0, WOp<T>{xj + c0, 1, k, cw});
-        if (j + 1 < n) // B_j^H x_{j+1}
-            wave_mm<T, 1, 1, true, false, 4>(cr, ci, WOp<T>{Bj + r0, 1, m, m - r0},
-                                             WOp<T>{xj + mk + c0, 1, k, cw}, m);
+    } else {
+        const int c0 = 16 * item, cw = min(16, k - c0);
+        constexpr int G = RM >= 4 ? 2 : 4;
+        for (int r0 = 0; r0 < m; r0 += 16 * RM) {
+            v4 cr[RM][1], ci[RM][1];
+            zero_acc<T, RM, 1>(cr, ci);
+            if (j > 0) // B_{j-1} x_{j-1}
+                wave_mm<T, RM, 1, false, false, G>(cr, ci, WOp<T>{Bm + (int64_t)r0 * m, m, 1, m - r0},
+                                                   WOp<T>{xj - mk + c0, 1, k, cw}, m);
+            wave_mm_herm_r<T, RM, G>(cr, ci, Aj, m, r0, WOp<T>{xj + c0, 1, k, cw});
+            if (j + 1 < n) // B_j^H x_{j+1}
+                wave_mm<T, RM, 1, true, false, G>(cr, ci, WOp<T>{Bj + r0, 1, m, m - r0},
+                                                  WOp<T>{xj + mk + c0, 1, k, cw}, m);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = r0 + MF<T>::row(kr, u), c = c0 + cc;
-            if (i < m && c < k) {
-                const cx<T> y = yj[i * k + c];
-                const cx<T> r{y.r - cr[0][0][u], y.i - ci[0][0][u]};
-                sr += r.r * r.r + r.i * r.i;
-                sy += y.r * y.r + y.i * y.i;
-                if (!R)
-                    continue;
-                if (r_f32)
-                    ((cx<float>*)R)[s.og + j * mk + i * k + c] = cx<float>{(float)r.r, (float)r.i};
-                else
-                    ((cx<double>*)R)[s.og + j * mk + i * k + c] = r;
-            }
+            for (int a = 0; a < RM; ++a)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = r0 + 16 * a + MF<T>::row(kr, u), c = c0 + cc;
+                    if (i < m && c < k) {
+                        const cx<T> y = yj[i * k + c];
+                        const cx<T> r{y.r - cr[a][0][u], y.i - ci[a][0][u]};
+                        sr += r.r * r.r + r.i * r.i;
+                        sy += y.r * y.r + y.i * y.i;
+                        if (rj)
+                            rj[i * k + c] = r;
+                    }
+                }
         }
     }
     sr = wave_sum(sr);
@@ -183,8 +250,9 @@ __global__ __launch_bounds__(64) void k_residual(const Seg* __restrict__ segs, i
     }
 }
 
-// norms[2 s + q] = sum over the n ceil(m / 16) partial-sum pairs of system s
-// of part[2 (ob0 + e) + q], in a fixed order (one work-group per system).
+// norms[2 s + q] = sum over the n resid_items(m, k) partial-sum pairs of
+// system s of part[2 (ob0 + e) + q], in a fixed order (one work-group per
+// system).
 __global__ __launch_bounds__(256) void k_norms(const Seg* __restrict__ segs, int nseg,
                                                const double* __restrict__ part,
                                                double* __restrict__ norms)
@@ -195,7 +263,7 @@ __global__ __launch_bounds__(256) void k_norms(const Seg* __restrict__ segs, int
         return;
     const Seg& s = segs[sidx];
     double a = 0.0, b = 0.0;
-    const int64_t ne = (int64_t)s.n * ((s.m + 15) >> 4);
+    const int64_t ne = (int64_t)s.n * resid_items(s.m, s.k);
     const double2* pp = (const double2*)part + s.ob0;
     // eight loads in flight per thread, summed in a fixed order
     constexpr int U = 8;
@@ -228,21 +296,6 @@ __global__ __launch_bounds__(256) void k_norms(const Seg* __restrict__ segs, int
     if (threadIdx.x == 0) {
         norms[2 * s.sys] = sh[0][0];
         norms[2 * s.sys + 1] = sh[1][0];
-    }
-}
-
-// x = (assign ? 0 : x) + d over a flat range of complex elements.
-__global__ __launch_bounds__(256) void k_update(cx<double>* __restrict__ x,
-                                                const cx<float>* __restrict__ d, int64_t n,
-                                                int assign)
-{
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * 256) {
-        const cx<float> v = d[e];
-        cx<double> o = assign ? cx<double>{0.0, 0.0} : x[e];
-        o.r += (double)v.r;
-        o.i += (double)v.i;
-        x[e] = o;
     }
 }
 
