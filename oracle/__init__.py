@@ -7,7 +7,8 @@ its Python binding) never calls it.
 ``cr_oracle.c`` implements block cyclic reduction for Hermitian positive
 definite block-tridiagonal systems from the paper (arXiv 1807.00370): the
 one-sided reduction (``solve_cr``), Algorithm 1 as printed with recursion on
-both half systems (``solve_pcr``), a block Cholesky cross-check
+both half systems (``solve_pcr``), the one-sided reduction finished by
+Algorithm 1 below a block count (``solve_hybrid``), a block Cholesky cross-check
 (``solve_thomas``), one split of Eq. (Formulas) (``split``), the residual of
 Eq. (Axb) and the adjoint (gradient) formulas.  All arithmetic is FP64.
 """
@@ -52,6 +53,8 @@ def _load():
             f = getattr(lib, name)
             f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.POINTER(_Info)]
             f.restype = ctypes.c_int
+        lib.cro_solve_hybrid.argtypes = [ctypes.c_int] * 4 + [P] * 4 + [ctypes.POINTER(_Info)]
+        lib.cro_solve_hybrid.restype = ctypes.c_int
         lib.cro_split.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [P] * 9
         lib.cro_split.restype = ctypes.c_int
         lib.cro_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [P] * 5
@@ -103,6 +106,19 @@ def solve_cr(A, B, y):
 def solve_pcr(A, B, y):
     """Algorithm 1 (recursion on both half systems); returns (x, info)."""
     return _solve("cro_solve_pcr", A, B, y)
+
+
+def solve_hybrid(A, B, y, tail_blocks):
+    """One-sided reduction until a level holds at most ``tail_blocks`` blocks,
+    then Algorithm 1 on that level's system; returns (x, info)."""
+    A, B, y, N, m, k = _shape(A, B, y)
+    x = np.empty((N, m, k), np.complex128)
+    info = _Info()
+    rc = _load().cro_solve_hybrid(N, m, k, int(tail_blocks), _ptr(A), _ptr(B), _ptr(y), _ptr(x),
+                                  ctypes.byref(info))
+    if rc != 0:
+        raise ValueError("cro_solve_hybrid: invalid arguments")
+    return x, dict(status=int(info.status), level=int(info.level), block=int(info.block))
 
 
 def solve_thomas(A, B, y):

@@ -19,7 +19,9 @@
  *   B + (j-1)*m*m  is B_j   (N-1 blocks)
  *   y + (j-1)*m*k  is y_j   (m x k, row-major), likewise x.
  *
- * Three solvers that reach the same x = A^{-1} y:
+ * Three solvers that reach the same x = A^{-1} y (and a hybrid of the first
+ * two, cro_solve_hybrid: the one-sided reduction down to a level of at most
+ * a given number of blocks, then Algorithm 1 on that level's system):
  *   cro_solve_cr      one-sided cyclic reduction: at each level the odd-index
  *                     blocks are eliminated through the even system of
  *                     Eq. (even) (formulas for V_j, F_j, v_j in Eq. (Formulas)),
@@ -291,11 +293,26 @@ static void reduce_off(int m, const elim *c, cplx *F)
 
 /* ------------------------------------------------------- one-sided reduction */
 
+static void pcr_solver(int n, int m, int k, const cplx *A, const cplx *B, const cplx *y,
+                       const int64_t *orig, cplx *x, int depth, cro_info *info);
+
+/* One level of the one-sided reduction.  hyb > 0: once a level holds at most
+ * hyb blocks, the rest of the system is solved by Algorithm 1 (both half
+ * systems at every level, pcr_solver) instead, with its levels numbered on
+ * from this one and its blocks in the original numbering. */
 static void cr_level(int n, int m, int k, const cplx *A, const cplx *B, const cplx *y,
-                     cplx *x, int level, int64_t ostride, cro_info *info)
+                     cplx *x, int level, int64_t ostride, int hyb, cro_info *info)
 {
     /* 0-based position p at this level is original block (p+1)*ostride. */
     const size_t mm = (size_t)m * m, mk = (size_t)m * k;
+    if (hyb > 0 && n <= hyb) {
+        int64_t *orig = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+        for (int p = 0; p < n; ++p)
+            orig[p] = (int64_t)(p + 1) * ostride;
+        pcr_solver(n, m, k, A, B, y, orig, x, level, info);
+        free(orig);
+        return;
+    }
     const int ne = (n + 1) / 2; /* odd 1-based positions: eliminated   */
     const int nk = n / 2;       /* even 1-based positions: kept, Eq. (even) */
     elim *E = (elim *)calloc((size_t)ne, sizeof(elim));
@@ -336,7 +353,7 @@ static void cr_level(int n, int m, int k, const cplx *A, const cplx *B, const cp
                 if (j + 1 < nk)
                     reduce_off(m, &E[j + 1], F + j * mm);
             }
-            cr_level(nk, m, k, V, F, v, xe, level + 1, ostride * 2, info);
+            cr_level(nk, m, k, V, F, v, xe, level + 1, ostride * 2, hyb, info);
             for (int j = 0; j < nk; ++j)
                 memcpy(x + (2 * j + 1) * mk, xe + j * mk, mk * sizeof(cplx));
             free(V); free(F); free(v); free(xe);
@@ -377,7 +394,19 @@ int cro_solve_cr(int N, int m, int k, const cplx *A, const cplx *B, const cplx *
     if (N < 1 || m < 1 || k < 1)
         return -1;
     info_clear(info);
-    cr_level(N, m, k, A, B, y, x, 0, 1, info);
+    cr_level(N, m, k, A, B, y, x, 0, 1, 0, info);
+    return 0;
+}
+
+/* The one-sided reduction until a level holds at most hyb blocks, then
+ * Algorithm 1 on that level's system (hyb = 0: one-sided throughout). */
+int cro_solve_hybrid(int N, int m, int k, int hyb, const cplx *A, const cplx *B, const cplx *y,
+                     cplx *x, cro_info *info)
+{
+    if (N < 1 || m < 1 || k < 1 || hyb < 0)
+        return -1;
+    info_clear(info);
+    cr_level(N, m, k, A, B, y, x, 0, 1, hyb, info);
     return 0;
 }
 

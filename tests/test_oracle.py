@@ -363,3 +363,52 @@ def test_residual_matches_dense_product(N, m, k):
     assert np.max(np.abs(stack(r) - (stack(s.y) - Dfull @ stack(x)))) > 1e-3
     rel = oracle.rel_residual(A, s.B, x, s.y)
     assert abs(rel - np.linalg.norm(ref) / np.linalg.norm(stack(s.y))) <= 1e-14 * rel
+
+
+# ------------------------------------------------------- hybrid schedule (CR then Algorithm 1)
+
+@pytest.mark.parametrize("N,m,k,H", [(64, 4, 1, 7), (100, 3, 2, 13), (777, 2, 2, 50),
+                                     (33, 4, 3, 33), (5, 2, 1, 2), (129, 1, 1, 16)])
+def test_hybrid_matches_dense_solve(N, m, k, H):
+    """The one-sided reduction switched to Algorithm 1 at a level of at most H
+    blocks reaches x = A^{-1} y (dense solve), for switch levels with odd and
+    even block counts."""
+    s = _sys(N, m, k, 1700 + N + H)
+    D = dense(s.A, s.B)
+    xd = np.linalg.solve(D, stack(s.y)).reshape(N, m, k)
+    x, info = oracle.solve_hybrid(s.A, s.B, s.y, H)
+    assert info == dict(status=0, level=-1, block=-1)
+    assert rel_err(x, xd) < 1e-12
+
+
+def test_hybrid_limits_are_the_two_schedules():
+    """H = 0 never switches (one-sided reduction); H >= N switches at level 0
+    (Algorithm 1): bit for bit the same results and records."""
+    s = _sys(300, 4, 2, 77)
+    t = _sys(300, 4, 2, 77, shift_scale=2.0)
+    for sysm in (s, t):
+        xc, ic = oracle.solve_cr(sysm.A, sysm.B, sysm.y)
+        xp, ip = oracle.solve_pcr(sysm.A, sysm.B, sysm.y)
+        xh0, ih0 = oracle.solve_hybrid(sysm.A, sysm.B, sysm.y, 0)
+        xh1, ih1 = oracle.solve_hybrid(sysm.A, sysm.B, sysm.y, 300)
+        assert ic == ih0 and ip == ih1
+        assert np.array_equal(xc, xh0, equal_nan=True) and np.array_equal(xp, xh1, equal_nan=True)
+
+
+@pytest.mark.parametrize("H", [16, 32])
+def test_hybrid_flag_scalar_golden(H):
+    """A_j = 1, B_j = 0.55, N = 64: with the switch at level 2 (H = 16) or 1
+    (H = 32), the level-2 factorization of Algorithm 1 meets original block 4
+    first with the hand-derived interior pivot 0.395 - 2 * 0.3025^2 / 0.395 <
+    0 (the system of blocks 4, 8, ... after two one-sided reductions, or the
+    even half system of blocks 2, 4, ... after one), so the record is
+    (level 2, block 4)."""
+    g = json.load(open(os.path.join(GOLDEN, "scalar_tridiagonal.json")))
+    N = g["breakdown_N"]
+    assert g["level2_interior_pivot"] < 0
+    A = np.ones((N, 1, 1), np.complex128)
+    B = np.full((N - 1, 1, 1), g["b"], np.complex128)
+    y = np.ones((N, 1, 1), np.complex128)
+    x, info = oracle.solve_hybrid(A, B, y, H)
+    assert info == dict(status=1, level=2, block=4)
+    assert np.isnan(x).all()
