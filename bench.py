@@ -626,7 +626,7 @@ def main():
     ap.add_argument("--N", type=int, default=65536)
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--k", type=int, default=16)
-    ap.add_argument("--forms", default="fp64,fp32_refine")
+    ap.add_argument("--forms", default="fp64,fp64_onesided,fp32_refine")
     ap.add_argument("--schedule", choices=("cr", "pcr"), default="cr",
                     help="cr: one-sided reduction (default); pcr: Algorithm 1 as printed (fp64)")
     ap.add_argument("--batch-half-max", type=int, default=4096,
@@ -690,13 +690,16 @@ def main():
     pcr = args.schedule == "pcr"
 
     def run_form(form, s, A, B, y, x, rtol, steps, warmup, tag):
-        if form == "fp64":
+        if form in ("fp64", "fp64_onesided"):
+            # fp64: one-sided levels, then Algorithm 1 below 64 blocks (the
+            # library default); fp64_onesided: one-sided throughout
             sol = Solver([s.N], [s.m], [s.k], dtype=torch.complex128, device=dev,
-                         schedule=args.schedule)
+                         schedule=args.schedule,
+                         pcr_tail_blocks=0 if form == "fp64_onesided" else None)
         else:
             sol = Solver([s.N], [s.m], [s.k], dtype=torch.complex128, precision="fp32_refine",
                          device=dev, rtol=rtol, max_refine=30, fp64_tail_blocks=TAIL)
-        tuning = (sol.autotune(A, B, y) if form == "fp64" and s.m <= 64 and not pcr
+        tuning = (sol.autotune(A, B, y) if form != "fp32_refine" and s.m <= 64 and not pcr
                   and not args.no_autotune else None)
         ms, ms_eager, per_step = time_form(torch, sol, A, B, y, x, steps, warmup)
         mean = _STEP_STATS["graph_mean"]
@@ -704,9 +707,11 @@ def main():
         if info["status"] != 0:
             raise SystemExit("%s: factorization failed: %s" % (tag, info))
         rel = sol.residual(A, B, x, y)[0]
-        iters = int(info["refine_iters"]) if form != "fp64" else 0
-        mod = pcr_model(s.N, s.m, s.k) if pcr else step_model(form, s.N, s.m, s.k, iters)
+        iters = int(info["refine_iters"]) if form == "fp32_refine" else 0
+        mod = pcr_model(s.N, s.m, s.k) if pcr else step_model(
+            "fp64" if form != "fp32_refine" else form, s.N, s.m, s.k, iters)
         rec = {
+            "pcr_tail_blocks": sol.pcr_tail_blocks,
             "ms_per_step": ms,
             "ms_per_step_mean": mean,
             "ms_per_step_eager": ms_eager,
@@ -715,12 +720,12 @@ def main():
             "rel_residual": rel,
             "certified": bool(rel <= rtol),
             "refine_iters": iters,
-            "fp64_fallback": int(info["fp64_fallback"]) if form != "fp64" else 0,
+            "fp64_fallback": int(info["fp64_fallback"]) if form == "fp32_refine" else 0,
             "workspace_bytes": sol.plan.ws_bytes,
             "kernel_ms_per_step": {kn: round(v[1], 4) for kn, v in per_step.items()},
             "kernel_launches_per_step": {kn: v[0] for kn, v in per_step.items()},
-            "roofline": roofline(per_step, mod, form == "fp64", ("pcr_" if pcr else "") + form,
-                                 (s.N, s.m, s.k)),
+            "roofline": roofline(per_step, mod, form != "fp32_refine",
+                                 ("pcr_" if pcr else "") + form, (s.N, s.m, s.k)),
             "model_bytes": sum(v[0] for v in mod.values()),
             "model_flops": sum(v[1] for v in mod.values()),
         }
@@ -791,7 +796,7 @@ def main():
             sk.A[:, idx, idx] -= c
             xo_k, io_k = oracle.solve_cr(sk.A, sk.B, sk.y)
             assert io_k["status"] == 0
-            for form in args.forms.split(","):
+            for form in [f for f in args.forms.split(",") if f != "fp64_onesided"]:
                 tag = "%s_kappa%s" % (form, kap)
                 rec, xh = run_form(form, sk, A, B, y, x, rtol, min(args.steps, 5), 2, tag)
                 rec["kappa"] = float(kap)
@@ -817,7 +822,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if best == "fp64" else "c64+f64",
+        "dtype": "c64+f64" if best == "fp32_refine" else "c128",
         "data": "synthetic",
         "config": {"workload": "%s, N=%d block rows, m=%d, k=%d, complex128 inputs, solved "
                                "to rel. residual <= %.3g (%s, %s form)" % (

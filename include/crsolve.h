@@ -115,6 +115,15 @@ typedef struct {
     int32_t max_refine;       /* FP32_REFINE correction cap, e.g. 30        */
     int32_t fp64_tail_blocks; /* FP32_REFINE: levels with <= this many
                                  blocks run in FP64, e.g. 8                 */
+    int32_t pcr_tail_blocks;  /* CR, NATIVE: once a level holds at most this
+                                 many blocks, the rest of the system is
+                                 solved by Algorithm 1 in place (both half
+                                 systems at every level, no back
+                                 substitution for those levels; Section 3,
+                                 "Time-Complexity"); the breakdown record
+                                 numbers its levels on from the switch.
+                                 0: one-sided throughout.  Must be 0 with
+                                 FP32_REFINE; ignored by PCR.               */
 } crsolve_desc;
 
 /* One per system, in device memory, written by factor / solve. */

@@ -37,7 +37,8 @@ class Desc(ctypes.Structure):
                 ("schedule", ctypes.c_int),
                 ("rtol", ctypes.c_double),
                 ("max_refine", ctypes.c_int32),
-                ("fp64_tail_blocks", ctypes.c_int32)]
+                ("fp64_tail_blocks", ctypes.c_int32),
+                ("pcr_tail_blocks", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -111,7 +112,7 @@ class Plan:
     """Owns a ``crsolve_plan`` (host metadata only)."""
 
     def __init__(self, Ns, ms, ks, dtype=C128, precision=PREC_NATIVE, schedule=SCHED_CR,
-                 rtol=1e-12, max_refine=30, fp64_tail_blocks=8):
+                 rtol=1e-12, max_refine=30, fp64_tail_blocks=8, pcr_tail_blocks=0):
         lib = load()
         self.Ns = [int(v) for v in Ns]
         self.ms = [int(v) for v in ms]
@@ -120,7 +121,7 @@ class Plan:
         arr = ctypes.c_int32 * self.batch
         self._N, self._m, self._k = arr(*self.Ns), arr(*self.ms), arr(*self.ks)
         d = Desc(self.batch, self._N, self._m, self._k, dtype, precision, schedule, rtol,
-                 max_refine, fp64_tail_blocks)
+                 max_refine, fp64_tail_blocks, pcr_tail_blocks)
         self.dtype, self.precision, self.schedule = dtype, precision, schedule
         h = ctypes.c_void_p()
         check("crsolve_plan_create", lib.crsolve_plan_create(ctypes.byref(d), ctypes.byref(h)))

@@ -91,6 +91,12 @@ struct LevelSpec {
     bool in64 = false, upd = false;
     int64_t ox = 0, xo = 0, xs = 1;
     int64_t oU = 0;
+    // Algorithm 1 in place (the PCR schedule, or the tail of the one-sided
+    // schedule): neighbour distance d, position p is original block
+    // obs (p + 1) (1-based)
+    bool pcr = false;
+    int d = 1;
+    int64_t obs = 1;
 };
 
 // Algorithm 1 in place: levels run until 2^l >= N, when every block is
@@ -133,6 +139,7 @@ struct crsolve_plan {
     double rtol = 1e-12;
     int max_refine = 30;
     int tail = 8;
+    int hyb = 0; // one-sided schedule: Algorithm 1 below this many blocks
 
     // packed caller arrays: complex-element offsets per system
     std::vector<int64_t> offA, offB, offy;
@@ -633,7 +640,7 @@ void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count cou
                     g.ox = v.ox; g.xo = v.xo; g.xs = v.xs;
                     g.oD = v.oD;
                     g.oU = v.oU;
-                    if (p->sched == CRSOLVE_SCHED_CR) {
+                    if (!v.pcr) {
                         g.d = 1;
                         g.e0 = 0; g.es = 2; g.ne = v.ne;
                         g.k0 = 1; g.ks = 2; g.nk = v.nk;
@@ -641,12 +648,12 @@ void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count cou
                         g.ob0 = 1ll << lvl;
                         g.obs = 1ll << lvl;
                     } else {
-                        g.d = (int)std::min<int64_t>(1ll << lvl, (int64_t)1 << 30);
+                        g.d = v.d;
                         g.e0 = 0; g.es = 1; g.ne = v.ne;
                         g.k0 = 0; g.ks = 1; g.nk = v.nk;
                         g.out_by_pos = 1;
-                        g.ob0 = 1;
-                        g.obs = 1;
+                        g.ob0 = v.obs;
+                        g.obs = v.obs;
                     }
                     g.w0 = L.total;
                     L.total += cnt;
@@ -731,7 +738,9 @@ int build_plan(crsolve_plan* p)
         const int64_t dtiles = (int64_t)((p->m[s] + 15) / 16) * 256; // inverse diagonal tiles
         std::vector<LevelSpec>& L = p->lv[s];
         if (p->sched == CRSOLVE_SCHED_CR) {
-            for (int v = p->N[s]; v > 0; v /= 2) {
+            // one-sided levels until the block count falls to hyb (if set)
+            int v = p->N[s];
+            for (; v > 0 && !(p->hyb > 0 && v <= p->hyb); v /= 2) {
                 LevelSpec ls;
                 ls.n = v;
                 ls.ne = (v + 1) / 2;
@@ -739,6 +748,7 @@ int build_plan(crsolve_plan* p)
                 ls.f64 = refine ? (v <= p->tail ? 1 : 0) : (f64native ? 1 : 0);
                 L.push_back(ls);
             }
+            const int ncr = (int)L.size(), nt = v; // Algorithm 1 tail of nt blocks
             int sw = -1;
             if (refine)
                 for (size_t l = 0; l < L.size(); ++l)
@@ -748,7 +758,7 @@ int build_plan(crsolve_plan* p)
                     }
             p->sw[s] = sw;
             // factor storage and reduced systems, per level in its precision
-            for (size_t l = 0; l < L.size(); ++l) {
+            for (size_t l = 0; l < (size_t)ncr; ++l) {
                 LevelSpec& v = L[l];
                 const size_t es = v.f64 ? e64 : e32;
                 v.oL = a.take(v.ne * mm, es);
@@ -759,11 +769,44 @@ int build_plan(crsolve_plan* p)
                 if (tiled(p->cls[s]))
                     v.oD = a.take(v.ne * dtiles, es);
             }
-            for (size_t l = 0; l < L.size(); ++l) {
+            for (size_t l = 0; l < (size_t)ncr; ++l) {
                 LevelSpec& v = L[l];
                 const size_t es = v.f64 ? e64 : e32;
                 v.og = a.take(v.ne * mk, es);
                 v.oyo = a.take(v.nk * mk, es);
+            }
+            if (nt > 0) {
+                // Algorithm 1 in place on the nt blocks of level ncr: every
+                // level keeps its own factors (so that a factorization can be
+                // solved again), the reduced systems alternate between two
+                // buffers
+                const size_t es = f64native ? e64 : e32;
+                const int D = pcr_depth(nt);
+                int64_t bA[2], bB[2], by[2];
+                for (int b = 0; b < 2; ++b) {
+                    bA[b] = a.take((int64_t)nt * mm, es);
+                    bB[b] = a.take((int64_t)nt * mm, es);
+                    by[b] = a.take((int64_t)nt * mk, es);
+                }
+                for (int i = 0; i <= D; ++i) {
+                    LevelSpec ls;
+                    ls.n = ls.ne = nt;
+                    ls.nk = i < D ? nt : 0;
+                    ls.f64 = f64native ? 1 : 0;
+                    ls.pcr = true;
+                    ls.d = (int)std::min<int64_t>(1ll << i, (int64_t)1 << 30);
+                    ls.obs = 1ll << ncr;
+                    ls.oL = a.take((int64_t)nt * mm, es);
+                    ls.oP = a.take((int64_t)nt * mm, es);
+                    ls.oQ = a.take((int64_t)nt * mm, es);
+                    ls.og = a.take((int64_t)nt * mk, es);
+                    if (tiled(p->cls[s]))
+                        ls.oD = a.take((int64_t)nt * dtiles, es);
+                    ls.oAo = bA[(i + 1) & 1];
+                    ls.oBo = bB[(i + 1) & 1];
+                    ls.oyo = by[(i + 1) & 1];
+                    L.push_back(ls);
+                }
             }
             // level inputs: level 0 reads the caller's arrays (the mixed
             // form's right-hand side is y in the first pass and the FP64
@@ -777,6 +820,11 @@ int build_plan(crsolve_plan* p)
                     v.oA = p->offA[s];
                     v.oB = p->offB[s];
                     v.oy = p->offy[s];
+                } else if (v.pcr && (int)l > ncr) {
+                    // later levels of the Algorithm 1 tail: the other buffer
+                    v.oA = L[l - 1].oAo;
+                    v.oB = L[l - 1].oBo;
+                    v.oy = L[l - 1].oyo;
                 } else if ((int)l == sw) {
                     // first FP64 level: its inputs are FP64 copies of the
                     // previous (FP32) level's reduced system
@@ -800,10 +848,13 @@ int build_plan(crsolve_plan* p)
                     v.oU = p->offy[s];
                 }
                 if (!refine) {
+                    // level l position p is block (p + 1) 2^l of x; the
+                    // Algorithm 1 tail keeps the numbering of its first level
+                    const int lx = v.pcr ? ncr : (int)l;
                     v.userX = true;
                     v.ox = p->offy[s];
-                    v.xo = (1ll << l) - 1;
-                    v.xs = 1ll << l;
+                    v.xo = (1ll << lx) - 1;
+                    v.xs = 1ll << lx;
                 } else if (sw < 0 || (int)l < sw) {
                     v.ox = (int64_t)(p->off_d32 / e32) + p->offy[s];
                     v.xo = (1ll << l) - 1;
@@ -844,6 +895,9 @@ int build_plan(crsolve_plan* p)
                 v.ox = p->offy[s];
                 v.xo = 0;
                 v.xs = 1;
+                v.pcr = true;
+                v.d = (int)std::min<int64_t>(1ll << l, (int64_t)1 << 30);
+                v.obs = 1;
                 L.push_back(v);
             }
         }
@@ -860,7 +914,7 @@ int build_plan(crsolve_plan* p)
     // every level; Algorithm 1 only solves the uncoupled blocks of its last
     // level (reassembly is the identity on the in-place layout).
     add_launches(p, p->back, maxlev, [&](int s, int l) -> int64_t {
-        if (p->sched == CRSOLVE_SCHED_PCR && l + 1 != (int)p->lv[s].size())
+        if (p->lv[s][l].pcr && l + 1 != (int)p->lv[s].size())
             return 0;
         return p->lv[s][l].ne;
     });
@@ -1497,6 +1551,11 @@ int validate(const crsolve_desc* d)
     if (d->schedule == CRSOLVE_SCHED_PCR &&
         (d->dtype != CRSOLVE_C128 || d->precision != CRSOLVE_PREC_NATIVE))
         return CRSOLVE_EUNSUPPORTED;
+    if (d->pcr_tail_blocks < 0)
+        return CRSOLVE_EINVAL;
+    if (d->pcr_tail_blocks > 0 && d->precision != CRSOLVE_PREC_NATIVE &&
+        d->schedule == CRSOLVE_SCHED_CR)
+        return CRSOLVE_EUNSUPPORTED;
     for (int s = 0; s < d->batch; ++s) {
         if (d->N[s] < 1 || d->m[s] < 1 || d->k[s] < 1)
             return CRSOLVE_EINVAL;
@@ -1527,6 +1586,7 @@ crsolve_plan* new_plan(const crsolve_desc* d, crsolve_precision prec, int* rc)
     p->rtol = d->rtol;
     p->max_refine = d->max_refine;
     p->tail = d->fp64_tail_blocks;
+    p->hyb = d->schedule == CRSOLVE_SCHED_CR ? d->pcr_tail_blocks : 0;
     p->cls.resize(p->batch);
     int64_t oa = 0, ob = 0, oy = 0, on = 0;
     for (int s = 0; s < p->batch; ++s) {

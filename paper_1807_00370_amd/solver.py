@@ -16,6 +16,7 @@ import torch
 from . import _lib
 
 _DT = {torch.complex128: _lib.C128, torch.complex64: _lib.C64}
+PCR_TAIL_DEFAULT = 64
 _PREC = {"native": _lib.PREC_NATIVE, "fp32_refine": _lib.PREC_FP32_REFINE}
 _SCHED = {"cr": _lib.SCHED_CR, "pcr": _lib.SCHED_PCR}
 
@@ -52,13 +53,20 @@ class Solver:
     """
 
     def __init__(self, Ns, ms, ks, dtype=torch.complex128, precision="native", schedule="cr",
-                 device="cuda", rtol=1e-12, max_refine=30, fp64_tail_blocks=8):
+                 device="cuda", rtol=1e-12, max_refine=30, fp64_tail_blocks=8,
+                 pcr_tail_blocks=None):
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.dtype = dtype
+        if pcr_tail_blocks is None:
+            # one-sided levels down to 64 blocks, then Algorithm 1 (fastest
+            # switch point measured at N = 65536, m = 32, k = 16); the mixed
+            # form stays one-sided
+            pcr_tail_blocks = PCR_TAIL_DEFAULT if (precision == "native" and schedule == "cr") else 0
+        self.pcr_tail_blocks = pcr_tail_blocks
         self.plan = _lib.Plan(Ns, ms, ks, _DT[dtype], _PREC[precision], _SCHED[schedule], rtol,
-                              max_refine, fp64_tail_blocks)
+                              max_refine, fp64_tail_blocks, pcr_tail_blocks)
         self.Ns, self.ms, self.ks = self.plan.Ns, self.plan.ms, self.plan.ks
         self.batch = self.plan.batch
         self.nA = sum(N * m * m for N, m in zip(self.Ns, self.ms))
@@ -202,10 +210,11 @@ def _shape_of(A, B, y):
     return N, m, y.shape[2]
 
 
-def solve(A, B, y, schedule="cr"):
+def solve(A, B, y, schedule="cr", pcr_tail_blocks=None):
     """Solve one system; returns (x, info_record).  Synchronizes for info."""
     N, m, k = _shape_of(A, B, y)
-    s = Solver([N], [m], [k], dtype=A.dtype, schedule=schedule, device=A.device)
+    s = Solver([N], [m], [k], dtype=A.dtype, schedule=schedule, device=A.device,
+               pcr_tail_blocks=pcr_tail_blocks)
     x = s.factor_solve(A, B, y)
     return x, s.info_host()[0]
 

@@ -92,3 +92,16 @@ def test_refine_fallback_region_is_one_system():
     whole64 = _lib.Plan(Ns, ms, ks).ws_bytes
     assert mixed < whole64 + big64
     assert mixed >= big64
+
+
+def test_pcr_tail_validation():
+    """The Algorithm 1 tail of the one-sided schedule: native plans only."""
+    p = _lib.Plan([1000], [16], [4], pcr_tail_blocks=256)
+    q = _lib.Plan([1000], [16], [4])
+    assert p.ws_bytes > 0 and q.ws_bytes > 0
+    with pytest.raises(_lib.CrsolveError) as e:
+        _lib.Plan([1000], [16], [4], precision=_lib.PREC_FP32_REFINE, pcr_tail_blocks=64)
+    assert e.value.code == _lib.EUNSUPPORTED
+    with pytest.raises(_lib.CrsolveError) as e:
+        _lib.Plan([1000], [16], [4], pcr_tail_blocks=-1)
+    assert e.value.code == _lib.EINVAL

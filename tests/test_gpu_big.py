@@ -40,7 +40,8 @@ def _solve(torch, dev, s, schedule="cr", dtype=None):
     from paper_1807_00370_amd.solver import Solver
     dt = dtype or torch.complex128
     A, B, y = (torch.from_numpy(np.ascontiguousarray(v)).to(dev).to(dt) for v in (s.A, s.B, s.y))
-    sol = Solver([s.N], [s.m], [s.k], dtype=dt, schedule=schedule, device=dev)
+    sol = Solver([s.N], [s.m], [s.k], dtype=dt, schedule=schedule, device=dev,
+                 pcr_tail_blocks=0)
     x = sol.factor_solve(A, B, y)
     torch.cuda.synchronize()
     return x.cpu().numpy().astype(np.complex128), _info(sol.info_host()[0])

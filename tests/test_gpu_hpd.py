@@ -46,7 +46,9 @@ def test_check_hpd_matches_eigenvalues(tdev, N, m, sign):
     At, Bt = (torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (A, s.B))
     ok, rec = check_hpd(At, Bt)
     assert ok == (sign > 0)
-    _, io = oracle.solve_cr(A, s.B, s.y)
+    # the default schedule: one-sided levels, then Algorithm 1 from 64 blocks
+    from paper_1807_00370_amd.solver import PCR_TAIL_DEFAULT
+    _, io = oracle.solve_hybrid(A, s.B, s.y, PCR_TAIL_DEFAULT)
     assert (int(rec["status"]), int(rec["level"]), int(rec["block"])) == \
         (io["status"], io["level"], io["block"])
 
