@@ -198,6 +198,23 @@ int crsolve_solve(const crsolve_plan *plan, void *ws, size_t ws_bytes, const voi
 int crsolve_factor_solve(crsolve_plan *plan, const void *A, const void *B, const void *y,
                          void *ws, size_t ws_bytes, void *x, crsolve_info *info, void *stream);
 
+/* crsolve_factor_solve without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  The workspace is a
+ * library-owned device array of 256 MiB per GPU (present from library load
+ * until the process ends; its address is looked up once per device on the
+ * first call there).  The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine.  NATIVE plans whose crsolve_workspace_size
+ * is at most 256 MiB (e.g. N = 4096, m = 16, k = 4); larger plans return
+ * CRSOLVE_EWORKSPACE, other precisions CRSOLVE_EUNSUPPORTED, before any
+ * device work.  Runs on the current device, whose stream `stream` must be;
+ * launches are eager (no graph, no per-kernel timing).  Every call on a GPU
+ * shares that GPU's array and leaves the last call's contents in it:
+ * calls that overlap in time on one GPU (other streams, other threads)
+ * race.  The factors do not stay usable for crsolve_solve. */
+int crsolve_factor_solve_noalloc(crsolve_plan *plan, const void *A, const void *B, const void *y,
+                                 void *x, crsolve_info *info, void *stream);
+
 /* Adjoint of x = A^{-1} y for a real loss L with gradient grad_x = dL/dx
  * (conjugate-Wirtinger convention, as PyTorch): solves A lam = grad_x with
  * the stored factors (A is Hermitian, so A^{-H} = A^{-1}) and forms

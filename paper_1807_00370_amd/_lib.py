@@ -22,7 +22,7 @@ OK, EINVAL, EHIP, EWORKSPACE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
 
 EXPORTS = ("crsolve_plan_create", "crsolve_workspace_size", "crsolve_factor", "crsolve_check_hpd",
            "crsolve_solve",
-           "crsolve_factor_solve", "crsolve_backward", "crsolve_residual", "crsolve_set_graphs",
+           "crsolve_factor_solve", "crsolve_factor_solve_noalloc", "crsolve_backward", "crsolve_residual", "crsolve_set_graphs",
            "crsolve_autotune", "crsolve_set_tuning", "crsolve_timing_enable",
            "crsolve_timing_read", "crsolve_plan_destroy", "crsolve_error_string")
 
@@ -82,6 +82,7 @@ def load():
     lib.crsolve_check_hpd.argtypes = [P, P, P, P, S, P, P]
     lib.crsolve_solve.argtypes = [P, P, S, P, P, P, P, P, P]
     lib.crsolve_factor_solve.argtypes = [P, P, P, P, P, S, P, P, P]
+    lib.crsolve_factor_solve_noalloc.argtypes = [P, P, P, P, P, P, P]
     lib.crsolve_backward.argtypes = [P, P, S, P, P, P, P, P, P]
     lib.crsolve_residual.argtypes = [P, P, S, P, P, P, P, ctypes.POINTER(ctypes.c_double), P]
     lib.crsolve_set_graphs.argtypes = [P, ctypes.c_int]
@@ -151,6 +152,12 @@ class Plan:
     def factor_solve(self, A, B, y, ws, x, info, stream):
         check("crsolve_factor_solve", load().crsolve_factor_solve(self._h, A, B, y, ws,
                                                                   self.ws_bytes, x, info, stream))
+
+    def factor_solve_noalloc(self, A, B, y, x, info, stream):
+        """factor_solve in the library's own device scratch array (no
+        workspace argument, nothing allocated)."""
+        check("crsolve_factor_solve_noalloc",
+              load().crsolve_factor_solve_noalloc(self._h, A, B, y, x, info, stream))
 
     def residual(self, ws, A, B, x, y, stream):
         """Per-system FP64 relative residuals (synchronizes)."""

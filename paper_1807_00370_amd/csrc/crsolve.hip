@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <cmath>
 #include <cstdint>
@@ -1628,6 +1629,36 @@ crsolve_plan* new_plan(const crsolve_desc* d, crsolve_precision prec, int* rc)
     return p;
 }
 
+// ------------------------------------------------- no-allocation entry point
+
+// Workspace of crsolve_factor_solve_noalloc: a file-scope device array that
+// every GPU the library runs on holds from module load to process end.  In
+// host code its name is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, looked up once per device.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr; // per device id, null until looked up
+
+int scratch_ptr(void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+        return CRSOLVE_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((size_t)dev >= g_scratch_ptr.size())
+        g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return CRSOLVE_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CRSOLVE_OK;
+}
+
 } // namespace
 
 // ======================================================================= C ABI
@@ -1937,6 +1968,33 @@ int crsolve_factor_solve(crsolve_plan* p, const void* A, const void* B, const vo
     if (rc == CRSOLVE_OK && p->sched == CRSOLVE_SCHED_CR)
         p->mark_factored(ws);
     return rc;
+}
+
+int crsolve_factor_solve_noalloc(crsolve_plan* p, const void* A, const void* B, const void* y,
+                                 void* x, crsolve_info* info, void* stream)
+{
+    if (!p)
+        return CRSOLVE_EINVAL;
+    if (p->prec != CRSOLVE_PREC_NATIVE)
+        return CRSOLVE_EUNSUPPORTED;
+    if (p->ws_bytes > kScratchBytes)
+        return CRSOLVE_EWORKSPACE;
+    const size_t es = io_esz(p);
+    if (!aligned(A, es) || (any_B(p) && !aligned(B, es)) || !aligned(y, es) || !aligned(x, es))
+        return CRSOLVE_EINVAL;
+    void* ws = nullptr;
+    int rc = scratch_ptr(&ws);
+    if (rc)
+        return rc;
+    // eager launches only: no graph, no timing events
+    Ctx c = make_ctx(p, ws, stream);
+    if ((rc = upload(p, c.ws, c.st)))
+        return rc;
+    const bool timing = tplan(p)->timing;
+    tplan(p)->timing = false;
+    enqueue_native_fs(c, A, B, y, x, info);
+    tplan(p)->timing = timing;
+    return last_err();
 }
 
 int crsolve_backward(const crsolve_plan* p, void* ws, size_t ws_bytes, const void* x,

@@ -105,3 +105,22 @@ def test_pcr_tail_validation():
     with pytest.raises(_lib.CrsolveError) as e:
         _lib.Plan([1000], [16], [4], pcr_tail_blocks=-1)
     assert e.value.code == _lib.EINVAL
+
+
+def test_noalloc_limits_checked_before_device_work():
+    """crsolve_factor_solve_noalloc rejects a plan whose workspace exceeds the
+    256 MiB scratch array, and non-native plans, before touching a GPU."""
+    import ctypes
+    lib = _lib.load()
+    fake = ctypes.c_void_p(1 << 20)
+    big = _lib.Plan([65536], [32], [16])
+    assert big.ws_bytes > (256 << 20)
+    assert lib.crsolve_factor_solve_noalloc(big._h, fake, fake, fake, fake, None, None) == \
+        _lib.EWORKSPACE
+    mixed = _lib.Plan([64], [4], [1], precision=_lib.PREC_FP32_REFINE)
+    assert lib.crsolve_factor_solve_noalloc(mixed._h, fake, fake, fake, fake, None, None) == \
+        _lib.EUNSUPPORTED
+    small = _lib.Plan([2048], [16], [4])
+    assert small.ws_bytes <= (256 << 20)
+    hdr = open(os.path.join(ROOT, "include", "crsolve.h")).read()
+    assert "256 MiB" in hdr
