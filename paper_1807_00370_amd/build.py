@@ -7,7 +7,6 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "crsolve.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "kernels.hpp"), os.path.join(ROOT, "include", "crsolve.h")]
 LIB = os.path.join(HERE, "libcrsolve.so")
 
 HIPCC_FLAGS = [

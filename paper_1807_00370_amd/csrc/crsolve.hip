@@ -1146,7 +1146,8 @@ void residual(const Ctx& c, const void* A, const void* B, const void* x, const v
     cx<double>* R = store_r ? (cx<double>*)c.ws : nullptr;
     for (const Launch& L : p->resid) {
         Timed tm(p, KID_RESIDUAL, c.st);
-        // row tiles per wave: one up to m = 16, two up to 32, then groups of four
+        // row tiles per wave: one up to m = 16, then groups of two (four
+        // would leave one wave per SIMD)
         const auto* Ad = (const cx<double>*)A;
         const auto* Bd = (const cx<double>*)B;
         const auto* Xd = (const cx<double>*)x;
@@ -1154,11 +1155,8 @@ void residual(const Ctx& c, const void* A, const void* B, const void* x, const v
         if (L.cls <= 2)
             hipLaunchKernelGGL(crs::k_residual<1>, dim3(grid8(L.total)), dim3(64), 0, c.st,
                                c.dsegs + L.seg0, L.nseg, L.total, Ad, Bd, Xd, Yd, R, part);
-        else if (L.cls == 3)
-            hipLaunchKernelGGL(crs::k_residual<2>, dim3(grid8(L.total)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, Ad, Bd, Xd, Yd, R, part);
         else
-            hipLaunchKernelGGL(crs::k_residual<4>, dim3(grid8(L.total)), dim3(64), 0, c.st,
+            hipLaunchKernelGGL(crs::k_residual<2>, dim3(grid8(L.total)), dim3(64), 0, c.st,
                                c.dsegs + L.seg0, L.nseg, L.total, Ad, Bd, Xd, Yd, R, part);
     }
     Timed tm(p, KID_NORMS, c.st);

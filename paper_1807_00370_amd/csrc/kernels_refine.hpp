@@ -145,7 +145,7 @@ __device__ __forceinline__ void wave_mm_herm_r(typename MF<T>::v4 (&cr)[RM][1],
 // with its RM row tiles at a time on MFMA.  part[2 (ob0 + it)] = the item's
 // ||r||_F^2, part[2 (ob0 + it) + 1] = the same for y.
 template <int RM>
-__global__ __launch_bounds__(64) void k_residual(const Seg* __restrict__ segs, int nseg,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_residual(const Seg* __restrict__ segs, int nseg,
                                                  int64_t total, const cx<double>* __restrict__ A,
                                                  const cx<double>* __restrict__ B,
                                                  const cx<double>* __restrict__ X,
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(64) void k_residual(const Seg* __restrict__ segs, i
         }
     } else {
         const int c0 = 16 * item, cw = min(16, k - c0);
-        constexpr int G = RM >= 4 ? 2 : 4;
+        constexpr int G = RM >= 2 ? 2 : 4;
         for (int r0 = 0; r0 < m; r0 += 16 * RM) {
             v4 cr[RM][1], ci[RM][1];
             zero_acc<T, RM, 1>(cr, ci);

@@ -217,6 +217,9 @@ def test_poisson_full_size_closed_form(tdev):
     res_rounded_exact = oracle.rel_residual(s.A, s.B, x_exact, s.y)
     print("residual %.3e, of the rounded exact solution %.3e" % (res, res_rounded_exact))
     assert res <= 16 * u * kappa
+    # and within a small factor of the floor that the rounded exact solution
+    # itself sets for this right-hand side
+    assert res <= 4 * res_rounded_exact
 
 
 def test_big_autotune_mixed_classes(tdev):
