@@ -24,9 +24,10 @@
  *   B : sum_s (N_s - 1) m_s^2 elements; B_j is the (j-1)-th block.
  *   y, x, grad_x, grad_y : sum_s N_s m_s k_s elements; block j is m x k.
  *   grad_A : like A (full blocks, not Hermitian-projected); grad_B : like B.
- * Element type: CRSOLVE_C128 -> double[2], CRSOLVE_C64 -> float[2].  With
+ * Element type: CRSOLVE_C128 -> double[2], CRSOLVE_C64 -> float[2],
+ * CRSOLVE_R64 -> double, CRSOLVE_R32 -> float.  With
  * CRSOLVE_PREC_FP32_REFINE the inputs and outputs are C128.
- * Every pointer must be 16-byte aligned (C128) or 8-byte aligned (C64).
+ * Every pointer must be aligned to its element size.
  *
  * OWNERSHIP: the caller owns every device buffer, including the workspace
  * (size from crsolve_workspace_size) and the crsolve_info array (one entry per
@@ -71,7 +72,13 @@
 extern "C" {
 #endif
 
-typedef enum { CRSOLVE_C128 = 0, CRSOLVE_C64 = 1 } crsolve_dtype;
+/* C128 / C64: complex double / float.  R64 / R32: real symmetric systems
+ * (the real case of Section 1: A_j symmetric, B_j real, conjugate
+ * transposes become transposes) in real double / float arrays; NATIVE and
+ * CR only, no crsolve_backward, no crsolve_residual.  The levels keep the
+ * complex workspace layout with zero imaginary parts; the products of the
+ * tiled kernels (blocks above 32) take one real MFMA per step. */
+typedef enum { CRSOLVE_C128 = 0, CRSOLVE_C64 = 1, CRSOLVE_R64 = 2, CRSOLVE_R32 = 3 } crsolve_dtype;
 
 /* NATIVE: every level in the dtype.  FP32_REFINE (C128 inputs only): the
  * reduction runs in complex FP32 except for levels with at most

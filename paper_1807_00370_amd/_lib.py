@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcrsolve.so")
 
-C128, C64 = 0, 1
+C128, C64, R64, R32 = 0, 1, 2, 3
 PREC_NATIVE, PREC_FP32_REFINE = 0, 1
 SCHED_CR, SCHED_PCR = 0, 1
 

@@ -71,6 +71,7 @@ struct Launch {
     bool userX;      // unknowns are written to the caller's x
     bool in64;       // the level's inputs are FP64 (FP32 levels round on load)
     bool upd;        // mixed form, level 0: corrections go into the FP64 x
+    bool inreal;     // the level's inputs are the caller's real arrays
 };
 
 struct CvtLaunch {
@@ -89,7 +90,7 @@ struct LevelSpec {
     int64_t oD = 0;                                                   // big blocks only
     int64_t oA = 0, oB = 0, oy = 0;                                   // inputs, level type
     bool userAB = false, userY = false, userX = false;
-    bool in64 = false, upd = false;
+    bool in64 = false, upd = false, inreal = false;
     int64_t ox = 0, xo = 0, xs = 1;
     int64_t oU = 0;
     // Algorithm 1 in place (the PCR schedule, or the tail of the one-sided
@@ -122,12 +123,13 @@ enum KernelId {
     KID_NORMS,
     KID_POTRF,
     KID_TRSM,
+    KID_REALOUT,
     KID_COUNT
 };
 const char* const kKernelName[KID_COUNT] = {"k_elim",       "k_reduce",   "k_back",
                                             "k_grad",       "k_flags_init", "k_finalize",
                                             "k_convert",    "k_residual", "k_norms",
-                                            "k_potrf_big",  "k_trsm_big"};
+                                            "k_potrf_big",  "k_trsm_big", "k_real_out"};
 
 } // namespace
 
@@ -135,6 +137,8 @@ struct crsolve_plan {
     int batch = 0;
     std::vector<int> N, m, k, cls;
     crsolve_dtype dtype = CRSOLVE_C128;
+    bool real = false;    // real symmetric dtypes (R64, R32)
+    size_t off_xc = 0;    // real dtypes: the unknowns, complex like y, before Re -> x
     crsolve_precision prec = CRSOLVE_PREC_NATIVE;
     crsolve_schedule sched = CRSOLVE_SCHED_CR;
     double rtol = 1e-12;
@@ -259,9 +263,11 @@ struct Timed {
 
 unsigned grid_of(int64_t total) { return (unsigned)std::min<int64_t>(total, kMaxGrid); }
 
-// Kernel dispatch per block-size class MT, element type T and level-input
-// type TI (TI = double for the FP32 levels that read FP64 inputs).
-template <class T, class TI = T>
+// Kernel dispatch per block-size class MT, element type T, level-input
+// element EI (cx<double> for the FP32 levels that read FP64 inputs, rl<T> for
+// the real dtypes' level 0) and real data (RE: the tiled kernels form one
+// real MFMA per product step).
+template <class T, class EI = cx<T>, bool RE = false>
 struct Disp {
     template <int MT>
     static void elim(const Launch& L, const Seg* segs, const void* inA, const void* inB,
@@ -269,19 +275,19 @@ struct Disp {
                      hipStream_t st, int variant, int nsplit)
     {
         if ((MT == 16 || MT == 32) && variant == 0) {
-            hipLaunchKernelGGL((crs::k_elim_mf<T, (MT == 16 || MT == 32) ? MT : 16, TI>),
+            hipLaunchKernelGGL((crs::k_elim_mf<T, (MT == 16 || MT == 32) ? MT : 16, EI>),
                                dim3((unsigned)(L.total * nsplit)), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, nsplit, (const cx<TI>*)inA,
-                               (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
+                               segs + L.seg0, L.nseg, L.total, nsplit, (const EI*)inA,
+                               (const EI*)inB, (const EI*)iny, (cx<T>*)W, flags, mat, rhs);
         } else if (MT <= 32 && variant == 0) {
-            hipLaunchKernelGGL((crs::k_elim_w<T, MT <= 32 ? MT : 32, TI>), dim3((unsigned)L.total), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
-                               (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_elim_w<T, MT <= 32 ? MT : 32, EI>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const EI*)inA,
+                               (const EI*)inB, (const EI*)iny, (cx<T>*)W, flags, mat, rhs);
         } else if constexpr (MT <= 32) { // blocks above 32 run the tiled kernels
             constexpr int PW = sizeof(T) == 8 ? 32 : 64;
-            hipLaunchKernelGGL((crs::k_elim<T, MT, kNT, PW, TI>), dim3(grid_of(L.total)), dim3(kNT), 0,
-                               st, segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
-                               (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_elim<T, MT, kNT, PW, EI>), dim3(grid_of(L.total)), dim3(kNT), 0,
+                               st, segs + L.seg0, L.nseg, L.total, (const EI*)inA,
+                               (const EI*)inB, (const EI*)iny, (cx<T>*)W, flags, mat, rhs);
         }
     }
     template <int MT>
@@ -290,17 +296,17 @@ struct Disp {
                        int variant)
     {
         if ((MT == 16 || MT == 32) && variant == 0) {
-            hipLaunchKernelGGL((crs::k_reduce_m<T, (MT == 16 || MT == 32) ? MT : 16, TI>), dim3((unsigned)L.total), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
-                               (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_reduce_m<T, (MT == 16 || MT == 32) ? MT : 16, EI>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const EI*)inA,
+                               (const EI*)iny, (cx<T>*)W, flags, mat, rhs);
         } else if (MT == 64) {
-            hipLaunchKernelGGL((crs::k_reduce_t<T, 64, TI>), dim3((unsigned)L.total), dim3(64), 0, st,
-                               segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
-                               (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_reduce_t<T, 64, EI>), dim3((unsigned)L.total), dim3(64), 0, st,
+                               segs + L.seg0, L.nseg, L.total, (const EI*)inA,
+                               (const EI*)iny, (cx<T>*)W, flags, mat, rhs);
         } else {
-            hipLaunchKernelGGL((crs::k_reduce<T, MT, kNT, TI>), dim3(grid_of(L.total)), dim3(kNT), 0,
-                               st, segs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
-                               (const cx<TI>*)iny, (cx<T>*)W, flags, mat, rhs);
+            hipLaunchKernelGGL((crs::k_reduce<T, MT, kNT, EI>), dim3(grid_of(L.total)), dim3(kNT), 0,
+                               st, segs + L.seg0, L.nseg, L.total, (const EI*)inA,
+                               (const EI*)iny, (cx<T>*)W, flags, mat, rhs);
         }
     }
     template <int MT>
@@ -403,7 +409,7 @@ constexpr int64_t kTailBlocks = 1024;
 
 bool mf_class(int cls) { return cls == 2 || cls == 3; }
 
-template <class T, class TI>
+template <class T, class EI, bool RE>
 void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const void* y, int mat,
               int rhs)
 {
@@ -418,12 +424,12 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
             // eight waves instead of four
             const unsigned nthr = L.total <= kPotrfWideBlocks ? 512 : 256;
             if (L.cls == kBig)
-                hipLaunchKernelGGL((crs::k_potrf_big<T, false, TI>), dim3((unsigned)L.total), dim3(nthr), 0,
-                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
+                hipLaunchKernelGGL((crs::k_potrf_big<T, false, EI, RE>), dim3((unsigned)L.total), dim3(nthr), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const EI*)inA,
                                    (cx<T>*)c.ws, c.flags);
             else
-                hipLaunchKernelGGL((crs::k_potrf_big<T, true, TI>), dim3((unsigned)L.total), dim3(nthr), 0,
-                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const cx<TI>*)inA,
+                hipLaunchKernelGGL((crs::k_potrf_big<T, true, EI, RE>), dim3((unsigned)L.total), dim3(nthr), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const EI*)inA,
                                    (cx<T>*)c.ws, c.flags);
         }
         const int ns = (mat ? 2 * b.S : 0) + (rhs ? b.K16 : 0);
@@ -432,13 +438,13 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
             const int ngrp = (ns + NC - 1) / NC;
             Timed tm(c.p, KID_TRSM, c.st, L.cls, L.f64);
             if (sizeof(T) == 8 && L.total >= kTrsmStripBlocks)
-                hipLaunchKernelGGL((crs::k_trsm_strip<T, TI>), dim3(grid8(L.total * ns)), dim3(64), 0,
+                hipLaunchKernelGGL((crs::k_trsm_strip<T, EI, RE>), dim3(grid8(L.total * ns)), dim3(64), 0,
                                    c.st, c.dsegs + L.seg0, L.nseg, L.total, ns, mat, rhs,
-                                   (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
+                                   (const EI*)inB, (const EI*)iny, (cx<T>*)c.ws, c.flags);
             else
-                hipLaunchKernelGGL((crs::k_trsm_big<T, TI>), dim3(grid8(L.total * ngrp)), dim3(64 * b.S),
+                hipLaunchKernelGGL((crs::k_trsm_big<T, EI, RE>), dim3(grid8(L.total * ngrp)), dim3(64 * b.S),
                                    0, c.st, c.dsegs + L.seg0, L.nseg, L.total, ngrp, mat, rhs,
-                                   (const cx<TI>*)inB, (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
+                                   (const EI*)inB, (const EI*)iny, (cx<T>*)c.ws, c.flags);
         }
         return;
     }
@@ -450,12 +456,12 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
         const int nst = (mat ? 2 * b.S : 0) + (rhs ? b.K16 : 0);
         nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nst, kTailWaves / L.total));
     }
-#define CALL(MT) Disp<T, TI>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st, v, nsplit)
+#define CALL(MT) Disp<T, EI, RE>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st, v, nsplit)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
 
-template <class T, class TI>
+template <class T, class EI, bool RE>
 void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int mat, int rhs)
 {
     const void* inA = L.userAB ? A : c.ws;
@@ -470,8 +476,8 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
         const bool staged = mat && L.cls == kBig;
         if (staged) {
             const int T64 = (b.S + 3) / 4, nm = T64 * (T64 + 1) / 2 + T64 * T64;
-            hipLaunchKernelGGL((crs::k_reduce_lds<T, TI>), dim3(grid8(L.total * nm)), dim3(256), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nm, (const cx<TI>*)inA,
+            hipLaunchKernelGGL((crs::k_reduce_lds<T, EI, RE>), dim3(grid8(L.total * nm)), dim3(256), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nm, (const EI*)inA,
                                (cx<T>*)c.ws, c.flags);
         }
         const int mt = mat && !staged ? 1 : 0;
@@ -479,44 +485,44 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
             // 32 < m <= 64: one wave per 16 x 16 tile (four times the waves of
             // the 32 x 32 tiles for these short contractions)
             const int nt = b.S * (b.S + 1) / 2 + b.S * b.S + (rhs ? b.S * b.K16 : 0);
-            hipLaunchKernelGGL((crs::k_reduce_big<T, 1, TI>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nt, 1, rhs, (const cx<TI>*)inA,
-                               (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 1, EI, RE>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, 1, rhs, (const EI*)inA,
+                               (const EI*)iny, (cx<T>*)c.ws, c.flags);
             return;
         }
         if (!mt && rhs && b.K16 == 1) {
             // y' alone with at most 16 columns: 16 x 16 tiles waste half as
             // many MFMA columns as 32 x 32 ones
             const int nt = b.S;
-            hipLaunchKernelGGL((crs::k_reduce_big<T, 1, TI>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nt, 0, rhs, (const cx<TI>*)inA,
-                               (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 1, EI, RE>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, 0, rhs, (const EI*)inA,
+                               (const EI*)iny, (cx<T>*)c.ws, c.flags);
             return;
         }
         const int nt = (mt ? b.T32 * (b.T32 + 1) / 2 + b.T32 * b.T32 : 0) + (rhs ? b.T32 * b.K32 : 0);
         if (nt > 0)
-            hipLaunchKernelGGL((crs::k_reduce_big<T, 2, TI>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nt, mt, rhs, (const cx<TI>*)inA,
-                               (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 2, EI, RE>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, mt, rhs, (const EI*)inA,
+                               (const EI*)iny, (cx<T>*)c.ws, c.flags);
         return;
     }
     if (mf_class(L.cls) && L.total <= kTailBlocks) {
         const BigDims b = big_dims(c.p, L);
         const int nt = (mat ? b.S * (b.S + 1) / 2 + b.S * b.S : 0) + (rhs ? b.S * b.K16 : 0);
         if (nt > 0)
-            hipLaunchKernelGGL((crs::k_reduce_big<T, 1, TI>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
-                               c.dsegs + L.seg0, L.nseg, L.total, nt, mat, rhs, (const cx<TI>*)inA,
-                               (const cx<TI>*)iny, (cx<T>*)c.ws, c.flags);
+            hipLaunchKernelGGL((crs::k_reduce_big<T, 1, EI, RE>), dim3(grid8(L.total * nt)), dim3(64), 0, c.st,
+                               c.dsegs + L.seg0, L.nseg, L.total, nt, mat, rhs, (const EI*)inA,
+                               (const EI*)iny, (cx<T>*)c.ws, c.flags);
         return;
     }
-#define CALL(MT) Disp<T, TI>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st, v)
+#define CALL(MT) Disp<T, EI, RE>::template reduce<MT>(L, c.dsegs, inA, iny, c.ws, c.flags, mat, rhs, c.st, v)
     CRS_BY_CLASS(L.cls, CALL)
 #undef CALL
 }
 
 // upd (mixed form): 0 plain back substitution; 1 / 2 the level-0 launches
 // assign / add their corrections to the caller's FP64 x.
-template <class T>
+template <class T, bool RE>
 void run_back(const Ctx& c, const Launch& L, void* x, int upd)
 {
     void* X = L.userX ? x : c.ws;
@@ -524,7 +530,7 @@ void run_back(const Ctx& c, const Launch& L, void* x, int upd)
     Timed tm(c.p, KID_BACK, c.st, L.cls, L.f64);
     if (tiled(L.cls)) {
         const BigDims b = big_dims(c.p, L);
-        hipLaunchKernelGGL((crs::k_back_big<T>), dim3(grid8(L.total * b.K16)), dim3(64 * b.S), 0, c.st,
+        hipLaunchKernelGGL((crs::k_back_big<T, RE>), dim3(grid8(L.total * b.K16)), dim3(64 * b.S), 0, c.st,
                            c.dsegs + L.seg0, L.nseg, L.total, b.K16, (const cx<T>*)c.ws, (cx<T>*)X,
                            c.flags, (cx<double>*)x, u);
         return;
@@ -588,6 +594,14 @@ __global__ void k_finalize(const unsigned long long* flags, crsolve_info* info, 
     }
 }
 
+// Real dtypes: x[e] = Re xc[e] over the unknowns of every system.
+template <class T>
+__global__ void k_real_out(const cx<T>* __restrict__ xc, T* __restrict__ x, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+        x[e] = xc[e].r;
+}
+
 // info[i].refine_iters / rel_residual from a host-filled table {iters, rel}.
 __global__ void k_set_refine(const double* tab, crsolve_info* info, int n)
 {
@@ -618,7 +632,7 @@ void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count cou
     for (int lvl = 0; lvl < nlev; ++lvl)
         for (int f = 0; f < 2; ++f)
             for (int c = 0; c < kNumCls; ++c) {
-                Launch L{lvl, c, f, (int)p->segs.size(), 0, 0, false, false, false, false, false};
+                Launch L{lvl, c, f, (int)p->segs.size(), 0, 0, false, false, false, false, false, false};
                 for (int s = 0; s < p->batch; ++s) {
                     if (p->cls[s] != c || lvl >= (int)p->lv[s].size())
                         continue;
@@ -663,6 +677,7 @@ void add_launches(crsolve_plan* p, std::vector<Launch>& out, int nlev, Count cou
                     L.userX = v.userX;
                     L.in64 = v.in64;
                     L.upd = v.upd;
+                    L.inreal = v.inreal;
                     p->segs.push_back(g);
                     ++L.nseg;
                 }
@@ -699,7 +714,7 @@ void add_cvt(crsolve_plan* p, std::vector<CvtLaunch>& out, const std::vector<Job
 int build_plan(crsolve_plan* p)
 {
     const bool refine = p->prec == CRSOLVE_PREC_FP32_REFINE;
-    const bool f64native = p->dtype == CRSOLVE_C128;
+    const bool f64native = p->dtype == CRSOLVE_C128 || p->dtype == CRSOLVE_R64;
     WsAlloc a;
     p->off_flags = a.off;
     a.off = align_up(a.off + sizeof(unsigned long long) * p->batch);
@@ -711,7 +726,7 @@ int build_plan(crsolve_plan* p)
     // the correction d (complex FP32, laid out like y), the residual r
     // (complex FP64, laid out like y), the info table and the fallback bits
     std::vector<int64_t> oxt(p->batch, 0);
-    const bool io64 = refine || f64native;
+    const bool io64 = refine || p->dtype == CRSOLVE_C128;
     if (io64) {
         p->off_part = a.off;
         // one pair of partial sums per residual work item
@@ -731,6 +746,12 @@ int build_plan(crsolve_plan* p)
         a.off = align_up(a.off + sizeof(double) * 2 * p->batch);
         p->off_fbits = a.off;
         a.off = align_up(a.off + sizeof(int32_t) * p->batch);
+    }
+    if (p->real) {
+        // the unknowns in the complex layout of the levels; their real parts
+        // go to the caller's real x at the end of every solve
+        p->off_xc = a.off;
+        a.off = align_up(a.off + (size_t)p->toty * (f64native ? e64 : e32));
     }
 
     int maxlev = 0;
@@ -816,6 +837,7 @@ int build_plan(crsolve_plan* p)
             for (size_t l = 0; l < L.size(); ++l) {
                 LevelSpec& v = L[l];
                 v.in64 = v.f64 || (refine && l == 0);
+                v.inreal = p->real && l == 0;
                 if (l == 0) {
                     v.userAB = v.userY = true;
                     v.oA = p->offA[s];
@@ -852,8 +874,9 @@ int build_plan(crsolve_plan* p)
                     // level l position p is block (p + 1) 2^l of x; the
                     // Algorithm 1 tail keeps the numbering of its first level
                     const int lx = v.pcr ? ncr : (int)l;
-                    v.userX = true;
-                    v.ox = p->offy[s];
+                    v.userX = !p->real;
+                    v.ox = p->real ? (int64_t)(p->off_xc / (f64native ? e64 : e32)) + p->offy[s]
+                                   : p->offy[s];
                     v.xo = (1ll << lx) - 1;
                     v.xs = 1ll << lx;
                 } else if (sw < 0 || (int)l < sw) {
@@ -951,7 +974,7 @@ int build_plan(crsolve_plan* p)
                     continue;
                 if (kind == 1 && !io64)
                     continue;
-                Launch L{0, c, f, (int)p->segs.size(), 0, 0, false, false, false, false, false};
+                Launch L{0, c, f, (int)p->segs.size(), 0, 0, false, false, false, false, false, false};
                 for (int s = 0; s < p->batch; ++s) {
                     if (p->cls[s] != c || (f == 1) != (p->lv[s][0].f64 == 1))
                         continue;
@@ -1043,6 +1066,10 @@ bool any_B(const crsolve_plan* p) { return p->totB > 0; }
 
 size_t io_esz(const crsolve_plan* p)
 {
+    if (p->dtype == CRSOLVE_R64)
+        return 8;
+    if (p->dtype == CRSOLVE_R32)
+        return 4;
     return (p->dtype == CRSOLVE_C128 || p->prec == CRSOLVE_PREC_FP32_REFINE) ? 16 : 8;
 }
 
@@ -1068,21 +1095,39 @@ void levels_down(const Ctx& c, const void* A, const void* B, const void* y, int 
     for (int l = 0; l < p->nlevels; ++l) {
         for (; ie < p->elim.size() && p->elim[ie].level == l; ++ie) {
             const Launch& L = p->elim[ie];
-            if (L.f64)
-                run_elim<double, double>(c, L, A, B, y, mat, rhs);
+            const bool re = p->real;
+            if (L.f64 && L.inreal)
+                run_elim<double, crs::rl<double>, true>(c, L, A, B, y, mat, rhs);
+            else if (L.f64 && re)
+                run_elim<double, cx<double>, true>(c, L, A, B, y, mat, rhs);
+            else if (L.f64)
+                run_elim<double, cx<double>, false>(c, L, A, B, y, mat, rhs);
+            else if (L.inreal)
+                run_elim<float, crs::rl<float>, true>(c, L, A, B, y, mat, rhs);
+            else if (re)
+                run_elim<float, cx<float>, true>(c, L, A, B, y, mat, rhs);
             else if (L.in64)
-                run_elim<float, double>(c, L, A, B, y, mat, rhs);
+                run_elim<float, cx<double>, false>(c, L, A, B, y, mat, rhs);
             else
-                run_elim<float, float>(c, L, A, B, y, mat, rhs);
+                run_elim<float, cx<float>, false>(c, L, A, B, y, mat, rhs);
         }
         for (; ir < p->reduce.size() && p->reduce[ir].level == l; ++ir) {
             const Launch& L = p->reduce[ir];
-            if (L.f64)
-                run_reduce<double, double>(c, L, A, y, mat, rhs);
+            const bool re = p->real;
+            if (L.f64 && L.inreal)
+                run_reduce<double, crs::rl<double>, true>(c, L, A, y, mat, rhs);
+            else if (L.f64 && re)
+                run_reduce<double, cx<double>, true>(c, L, A, y, mat, rhs);
+            else if (L.f64)
+                run_reduce<double, cx<double>, false>(c, L, A, y, mat, rhs);
+            else if (L.inreal)
+                run_reduce<float, crs::rl<float>, true>(c, L, A, y, mat, rhs);
+            else if (re)
+                run_reduce<float, cx<float>, true>(c, L, A, y, mat, rhs);
             else if (L.in64)
-                run_reduce<float, double>(c, L, A, y, mat, rhs);
+                run_reduce<float, cx<double>, false>(c, L, A, y, mat, rhs);
             else
-                run_reduce<float, float>(c, L, A, y, mat, rhs);
+                run_reduce<float, cx<float>, false>(c, L, A, y, mat, rhs);
         }
         if (l + 1 < (int)p->cvt_factor_sw.size()) {
             if (mat)
@@ -1110,14 +1155,24 @@ void levels_up(const Ctx& c, void* x, int upd = 0)
                 for (const CvtLaunch& cl : p->scatter_sw[next - 1])
                     run_cvt(c, cl, nullptr, nullptr, nullptr);
         if (L.f64)
-            run_back<double>(c, L, x, upd);
+            p->real ? run_back<double, true>(c, L, x, upd) : run_back<double, false>(c, L, x, upd);
         else
-            run_back<float>(c, L, x, upd);
+            p->real ? run_back<float, true>(c, L, x, upd) : run_back<float, false>(c, L, x, upd);
     }
     for (; next > 0; --next)
         if (next - 1 < nsc)
             for (const CvtLaunch& cl : p->scatter_sw[next - 1])
                 run_cvt(c, cl, nullptr, nullptr, nullptr);
+    if (p->real) {
+        Timed tm(p, KID_REALOUT, c.st);
+        const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((p->toty + 255) / 256, 1 << 16));
+        if (p->dtype == CRSOLVE_R64)
+            hipLaunchKernelGGL(k_real_out<double>, dim3(g), dim3(256), 0, c.st,
+                               (const cx<double>*)(c.ws + p->off_xc), (double*)x, p->toty);
+        else
+            hipLaunchKernelGGL(k_real_out<float>, dim3(g), dim3(256), 0, c.st,
+                               (const cx<float>*)(c.ws + p->off_xc), (float*)x, p->toty);
+    }
 }
 
 void finalize(const Ctx& c, crsolve_info* info, int fb)
@@ -1536,7 +1591,8 @@ int validate(const crsolve_desc* d)
 {
     if (!d || d->batch < 1 || !d->N || !d->m || !d->k)
         return CRSOLVE_EINVAL;
-    if (d->dtype != CRSOLVE_C128 && d->dtype != CRSOLVE_C64)
+    if (d->dtype != CRSOLVE_C128 && d->dtype != CRSOLVE_C64 && d->dtype != CRSOLVE_R64 &&
+        d->dtype != CRSOLVE_R32)
         return CRSOLVE_EINVAL;
     if (d->precision != CRSOLVE_PREC_NATIVE && d->precision != CRSOLVE_PREC_FP32_REFINE)
         return CRSOLVE_EINVAL;
@@ -1552,6 +1608,9 @@ int validate(const crsolve_desc* d)
         return CRSOLVE_EUNSUPPORTED;
     if (d->pcr_tail_blocks < 0)
         return CRSOLVE_EINVAL;
+    if ((d->dtype == CRSOLVE_R64 || d->dtype == CRSOLVE_R32) &&
+        (d->precision != CRSOLVE_PREC_NATIVE || d->schedule != CRSOLVE_SCHED_CR))
+        return CRSOLVE_EUNSUPPORTED;
     if (d->pcr_tail_blocks > 0 && d->precision != CRSOLVE_PREC_NATIVE &&
         d->schedule == CRSOLVE_SCHED_CR)
         return CRSOLVE_EUNSUPPORTED;
@@ -1580,6 +1639,7 @@ crsolve_plan* new_plan(const crsolve_desc* d, crsolve_precision prec, int* rc)
     p->m.assign(d->m, d->m + d->batch);
     p->k.assign(d->k, d->k + d->batch);
     p->dtype = d->dtype;
+    p->real = d->dtype == CRSOLVE_R64 || d->dtype == CRSOLVE_R32;
     p->prec = prec;
     p->sched = d->schedule;
     p->rtol = d->rtol;
@@ -2000,7 +2060,7 @@ int crsolve_backward(const crsolve_plan* p, void* ws, size_t ws_bytes, const voi
 {
     if (!p)
         return CRSOLVE_EINVAL;
-    if (p->sched != CRSOLVE_SCHED_CR || p->prec != CRSOLVE_PREC_NATIVE)
+    if (p->sched != CRSOLVE_SCHED_CR || p->prec != CRSOLVE_PREC_NATIVE || p->real)
         return CRSOLVE_EUNSUPPORTED;
     int rc = check_ws(p, ws, ws_bytes);
     if (rc)

@@ -37,12 +37,26 @@ struct alignas(2 * sizeof(T)) cx {
     T r, i;
 };
 
-// Element of a level input read in another precision (the mixed form's FP32
-// levels read the caller's FP64 arrays at level 0 and round on load).
+// Element of a real array (the real symmetric dtypes) read where complex
+// elements are expected: the imaginary part is a constant zero.
+template <class T>
+struct rl {
+    T r;
+    static constexpr T i = T(0);
+};
+
+// Element of a level input read in another precision or kind (the mixed
+// form's FP32 levels read the caller's FP64 arrays at level 0 and round on
+// load; the real dtypes read real arrays).
 template <class T, class S>
 __device__ __forceinline__ cx<T> cvt(const cx<S> v)
 {
     return cx<T>{(T)v.r, (T)v.i};
+}
+template <class T, class S>
+__device__ __forceinline__ cx<T> cvt(const rl<S> v)
+{
+    return cx<T>{(T)v.r, T(0)};
 }
 
 // c -= a * b
@@ -158,11 +172,11 @@ __device__ __forceinline__ int find_seg(const Seg* __restrict__ s, int nseg, int
 
 // ----------------------------------------------------------------- k_elim
 
-template <class T, int MT, int NT, int PW, class TI = T>
+template <class T, int MT, int NT, int PW, class EI = cx<T>>
 __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int nseg, int64_t total,
-                                             const cx<TI>* __restrict__ inA,
-                                             const cx<TI>* __restrict__ inB,
-                                             const cx<TI>* __restrict__ iny, cx<T>* __restrict__ W,
+                                             const EI* __restrict__ inA,
+                                             const EI* __restrict__ inB,
+                                             const EI* __restrict__ iny, cx<T>* __restrict__ W,
                                              unsigned long long* __restrict__ flags, int with_mat,
                                              int with_rhs)
 {
@@ -185,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int n
         cx<T>* Lg = W + s.oL + t * (int64_t)m * m;
         __syncthreads();
         if (with_mat) {
-            const cx<TI>* Ap = inA + s.oA + (int64_t)p * m * m;
+            const EI* Ap = inA + s.oA + (int64_t)p * m * m;
             for (int e = tid; e < m * m; e += NT)
                 sL[(e / m) * LD + e % m] = cvt<T>(Ap[e]);
             if (tid == 0)
@@ -238,7 +252,7 @@ __global__ __launch_bounds__(NT) void k_elim(const Seg* __restrict__ segs, int n
         // forward substitution on the operands of Eq. (Formulas)
         for (int src = 0; src < 3; ++src) {
             int ncol, ldg;
-            const cx<TI>* G;
+            const EI* G;
             cx<T>* out;
             bool herm = false;
             if (src == 0) {
@@ -350,10 +364,10 @@ __device__ __forceinline__ void gram_sub(cx<T> (&acc)[R][R], const cx<T>* __rest
     }
 }
 
-template <class T, int MT, int NT, class TI = T>
+template <class T, int MT, int NT, class EI = cx<T>>
 __global__ __launch_bounds__(NT) void k_reduce(const Seg* __restrict__ segs, int nseg, int64_t total,
-                                               const cx<TI>* __restrict__ inA,
-                                               const cx<TI>* __restrict__ iny,
+                                               const EI* __restrict__ inA,
+                                               const EI* __restrict__ iny,
                                                cx<T>* __restrict__ W,
                                                const unsigned long long* __restrict__ flags,
                                                int with_mat, int with_rhs)
@@ -380,7 +394,7 @@ __global__ __launch_bounds__(NT) void k_reduce(const Seg* __restrict__ segs, int
             continue; // the level's elimination broke down: stop this system
         if (with_mat) {
             cx<T> acc[R][R];
-            const cx<TI>* Aq = inA + s.oA + q * mm;
+            const EI* Aq = inA + s.oA + q * mm;
 #pragma unroll
             for (int i = 0; i < R; ++i)
 #pragma unroll
@@ -429,7 +443,7 @@ __global__ __launch_bounds__(NT) void k_reduce(const Seg* __restrict__ segs, int
             }
         }
         if (with_rhs) {
-            const cx<TI>* yq = iny + s.oy + q * mk;
+            const EI* yq = iny + s.oy + q * mk;
             cx<T>* yo = W + s.oyo + oi * mk;
             for (int c0 = 0; c0 < k; c0 += 16 * R) {
                 const int cw = min(16 * R, k - c0);

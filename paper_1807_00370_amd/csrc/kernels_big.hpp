@@ -130,9 +130,10 @@ __device__ __forceinline__ void wave_mm(typename MF<T>::v4 (&cr)[RM][RN],
     }
 }
 
-// acc += opA(A) opB(B) in the 3M form, operands as in wave_mm.
-template <class T, int RM, int RN, bool CA, bool CB, int G>
-__device__ __forceinline__ void wave_mm3(Acc3<T, RM, RN>& acc, const WOp<T> A, const WOp<T> B,
+// acc += opA(A) opB(B) in the 3M form (one real MFMA per step for real
+// data, RE), operands as in wave_mm.
+template <class T, int RM, int RN, bool CA, bool CB, int G, bool RE = false>
+__device__ __forceinline__ void wave_mm3(Acc3<T, RM, RN, RE>& acc, const WOp<T> A, const WOp<T> B,
                                          int kd)
 {
     const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
@@ -190,8 +191,10 @@ __device__ __forceinline__ void wave_mm3(Acc3<T, RM, RN>& acc, const WOp<T> A, c
 #pragma unroll
                 for (int j = 0; j < RN; ++j) {
                     acc.t1[i][j] = MF<T>::mma(ar[i], br[j], acc.t1[i][j]);
-                    acc.t2[i][j] = MF<T>::mma(ai[i], bi[j], acc.t2[i][j]);
-                    acc.t3[i][j] = MF<T>::mma(as[i], bs[j], acc.t3[i][j]);
+                    if constexpr (!RE) {
+                        acc.t2[i][j] = MF<T>::mma(ai[i], bi[j], acc.t2[i][j]);
+                        acc.t3[i][j] = MF<T>::mma(as[i], bs[j], acc.t3[i][j]);
+                    }
                 }
         }
     };
@@ -295,9 +298,9 @@ __device__ __forceinline__ void wave_lds_sync()
 // three waves per SIMD; otherwise the rows go through LDS and the compiler
 // keeps two waves per SIMD.  The first is faster at m <= 64 (the diagonal
 // tiles are a larger share of the work), the second at m = 256.
-template <class T, bool RB, class TI = T>
+template <class T, bool RB, class EI = cx<T>, bool RE = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2, 8))) void k_potrf_big(const Seg* __restrict__ segs, int nseg,
-                                                   int64_t total, const cx<TI>* __restrict__ inA,
+                                                   int64_t total, const EI* __restrict__ inA,
                                                    cx<T>* __restrict__ W,
                                                    unsigned long long* __restrict__ flags)
 {
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2,
     if ((flags[s.sys] >> 40) < (unsigned long long)s.level)
         return; // broke down at an earlier level
     const int64_t mm = (int64_t)m * m;
-    const cx<TI>* Ap = inA + s.oA + (int64_t)p * mm;
+    const EI* Ap = inA + s.oA + (int64_t)p * mm;
     cx<T>* Lg = W + s.oL + t * mm;
     cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
     if (tid == 0)
@@ -327,9 +330,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2,
         // panel column I: S_R = A[R][I] - L[R][<I] L[I][<I]^H for R >= I (the
         // Hermitian reading of A: lower triangle of the diagonal tile only)
         for (int R = I + wv; R < S; R += nw) {
-            Acc3<T, 1, 1> acc;
+            Acc3<T, 1, 1, RE> acc;
             acc.zero();
-            wave_mm3<T, 1, 1, false, true, 4>(acc, WOp<T>{Lg + (int64_t)16 * R * m, m, 1, m - 16 * R},
+            wave_mm3<T, 1, 1, false, true, 4, RE>(acc, WOp<T>{Lg + (int64_t)16 * R * m, m, 1, m - 16 * R},
                                               WOp<T>{Lg + (int64_t)c0 * m, m, 1, m - c0}, c0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -424,9 +427,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2,
         __syncthreads();
         // tiles below the diagonal: L[R][I] = S_R D_I^H, in place
         for (int R = I + 1 + wv; R < S; R += nw) {
-            Acc3<T, 1, 1> acc;
+            Acc3<T, 1, 1, RE> acc;
             acc.zero();
-            wave_mm3<T, 1, 1, false, true, 4>(acc,
+            wave_mm3<T, 1, 1, false, true, 4, RE>(acc,
                                               WOp<T>{Lg + (int64_t)16 * R * m + c0, m, 1, m - 16 * R},
                                               WOp<T>{sD, 17, 1, 16}, min(16, m - c0));
 #pragma unroll
@@ -460,11 +463,11 @@ constexpr int trsm_strips()
 // X_J = D_J (G_J - acc_J), the accumulator being the right operand (see the
 // note in k_elim_mf), stores it and publishes it in LDS; every wave I > J
 // then accumulates acc_I += L_IJ X_J (its operand loaded one step ahead).
-template <class T, class TI = T>
+template <class T, class EI = cx<T>, bool RE = false>
 __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int ngrp, int with_mat,
-                                                   int with_rhs, const cx<TI>* __restrict__ inB,
-                                                   const cx<TI>* __restrict__ iny,
+                                                   int with_rhs, const EI* __restrict__ inB,
+                                                   const EI* __restrict__ iny,
                                                    cx<T>* __restrict__ W,
                                                    const unsigned long long* __restrict__ flags)
 {
@@ -490,7 +493,7 @@ __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs,
     // per strip slot b: element (r, c) of the right-hand side is
     // G[b][r * gr[b] + c * gc[b]] (conjugated for B_p^H), the solution goes
     // to out[b][r * ld[b] + c], columns c0[b] .. c0[b] + nc[b] - 1
-    const cx<TI>* G[NC];
+    const EI* G[NC];
     cx<T>* out[NC];
     int gr[NC], gc[NC], ld[NC], c0[NC], nc[NC];
     bool cj[NC], on[NC];
@@ -581,9 +584,11 @@ __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs,
                 for (int v = 0; v < 4; ++v) {
                     const cx<T> q = aD[v];
                     xr = MF<T>::mma(q.r, ar[b][v], xr);
-                    xr = MF<T>::mma(-q.i, ai[b][v], xr);
-                    xi = MF<T>::mma(q.r, ai[b][v], xi);
-                    xi = MF<T>::mma(q.i, ar[b][v], xi);
+                    if constexpr (!RE) {
+                        xr = MF<T>::mma(-q.i, ai[b][v], xr);
+                        xi = MF<T>::mma(q.r, ai[b][v], xi);
+                        xi = MF<T>::mma(q.i, ar[b][v], xi);
+                    }
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -605,9 +610,11 @@ __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs,
                 for (int q = 0; q < 4; ++q) {
                     const cx<T> x = sx[b][(4 * q + kr) * 16 + cc];
                     ar[b] = MF<T>::mma(-a[q].r, x.r, ar[b]);
-                    ar[b] = MF<T>::mma(a[q].i, x.i, ar[b]);
-                    ai[b] = MF<T>::mma(-a[q].r, x.i, ai[b]);
-                    ai[b] = MF<T>::mma(-a[q].i, x.r, ai[b]);
+                    if constexpr (!RE) {
+                        ar[b] = MF<T>::mma(a[q].i, x.i, ar[b]);
+                        ai[b] = MF<T>::mma(-a[q].r, x.i, ai[b]);
+                        ai[b] = MF<T>::mma(-a[q].i, x.r, ai[b]);
+                    }
                 }
             }
         }
@@ -620,11 +627,11 @@ __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs,
 // a block: with_mat gives 2 S strips (columns of B_p^H, then of B_{p-d}),
 // with_rhs ceil(k / 16) strips of y_p after them.  Used for FP64 levels with
 // many blocks, where the work-group form's idle waves would cost throughput.
-template <class T, class TI = T>
+template <class T, class EI = cx<T>, bool RE = false>
 __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs, int nseg,
                                                  int64_t total, int nstrip, int with_mat,
-                                                 int with_rhs, const cx<TI>* __restrict__ inB,
-                                                 const cx<TI>* __restrict__ iny,
+                                                 int with_rhs, const EI* __restrict__ inB,
+                                                 const EI* __restrict__ iny,
                                                  cx<T>* __restrict__ W,
                                                  const unsigned long long* __restrict__ flags)
 {
@@ -661,7 +668,7 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
     }
     const int nc = min(16, (src == 2 ? k : m) - c0);
     // element (r, c) of the right-hand side is G[r * gr + c * gc]
-    const cx<TI>* G;
+    const EI* G;
     int gr, gc;
     cx<T>* out;
     if (src == 0) {
@@ -685,15 +692,15 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
     const cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
     for (int I = 0; I < S; ++I) {
         const int r0 = 16 * I;
-        Acc3<T, 1, 1> acc;
+        Acc3<T, 1, 1, RE> acc;
         acc.zero();
-        wave_mm3<T, 1, 1, false, false, 4>(acc, WOp<T>{Lg + (int64_t)r0 * m, m, 1, m - r0},
-                                           WOp<T>{out + c0, 1, ldo, nc}, r0);
+        wave_mm3<T, 1, 1, false, false, 4, RE>(acc, WOp<T>{Lg + (int64_t)r0 * m, m, 1, m - r0},
+                                               WOp<T>{out + c0, 1, ldo, nc}, r0);
         // w = G_I - acc stays in the accumulator layout: register v of lane
         // (kr, cc) holds row MF::row(kr, v) of column cc, which is the right
         // operand of contraction step v once the left operand D_I supplies
         // column MF::row(kr, v) of its row cc
-        Acc3<T, 1, 1> x;
+        Acc3<T, 1, 1, RE> x;
         x.zero();
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -703,9 +710,7 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
                 g.i = -g.i;
             const T br = g.r - acc.re(0, 0, v), bi = g.i - acc.im(0, 0, v);
             const cx<T> a = Dg[I * 256 + cc * 16 + rr];
-            x.t1[0][0] = MF<T>::mma(a.r, br, x.t1[0][0]);
-            x.t2[0][0] = MF<T>::mma(a.i, bi, x.t2[0][0]);
-            x.t3[0][0] = MF<T>::mma(a.r + a.i, br + bi, x.t3[0][0]);
+            x.step(0, 0, a.r, a.i, br, bi);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -726,11 +731,11 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
 // TW = 1 the blocks of 32 < m <= 64, the right-hand sides with k <= 16 of
 // larger blocks, and the levels of m <= 32 with too few blocks to fill the
 // GPU one wave per block.
-template <class T, int TW, class TI = T>
+template <class T, int TW, class EI = cx<T>, bool RE = false>
 __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int ntile, int with_mat,
-                                                   int with_rhs, const cx<TI>* __restrict__ inA,
-                                                   const cx<TI>* __restrict__ iny,
+                                                   int with_rhs, const EI* __restrict__ inA,
+                                                   const EI* __restrict__ iny,
                                                    cx<T>* __restrict__ W,
                                                    const unsigned long long* __restrict__ flags)
 {
@@ -782,16 +787,16 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
     const cx<T>* Qr = W + s.oQ + tr * mm;
     const cx<T>* Pr = W + s.oP + tr * mm;
     const int i0 = TT * ti, j0 = TT * tj;
-    Acc3<T, TW, TW> acc;
+    Acc3<T, TW, TW, RE> acc;
     acc.zero();
     if (kind == 0) {
         if (hasL)
-            wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Pl + i0, 1, m, m - i0},
+            wave_mm3<T, TW, TW, true, false, 2 / TW, RE>(acc, WOp<T>{Pl + i0, 1, m, m - i0},
                                              WOp<T>{Pl + j0, 1, m, m - j0}, m);
         if (hasR)
-            wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
+            wave_mm3<T, TW, TW, true, false, 2 / TW, RE>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{Qr + j0, 1, m, m - j0}, m);
-        const cx<TI>* Aq = inA + s.oA + q * mm;
+        const EI* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll
         for (int a = 0; a < TW; ++a)
@@ -809,7 +814,7 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                     }
                 }
     } else if (kind == 1) {
-        wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Pr + i0, 1, m, m - i0},
+        wave_mm3<T, TW, TW, true, false, 2 / TW, RE>(acc, WOp<T>{Pr + i0, 1, m, m - i0},
                                          WOp<T>{Qr + j0, 1, m, m - j0}, m);
         cx<T>* Fo = W + s.oBo + oi * mm;
 #pragma unroll
@@ -826,12 +831,12 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
         const cx<T>* gl = W + s.og + tl * mk;
         const cx<T>* gr = W + s.og + tr * mk;
         if (hasL)
-            wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Pl + i0, 1, m, m - i0},
+            wave_mm3<T, TW, TW, true, false, 2 / TW, RE>(acc, WOp<T>{Pl + i0, 1, m, m - i0},
                                              WOp<T>{gl + j0, 1, k, k - j0}, m);
         if (hasR)
-            wave_mm3<T, TW, TW, true, false, 2 / TW>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
+            wave_mm3<T, TW, TW, true, false, 2 / TW, RE>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{gr + j0, 1, k, k - j0}, m);
-        const cx<TI>* yq = iny + s.oy + q * mk;
+        const EI* yq = iny + s.oy + q * mk;
         cx<T>* vo = W + s.oyo + oi * mk;
 #pragma unroll
         for (int a = 0; a < TW; ++a)
@@ -861,10 +866,10 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
 // buffers, one barrier per panel).  Items per kept block: the
 // NT (NT + 1) / 2 lower tiles of A', then the NT^2 tiles of B' (NT =
 // ceil(m / 64)).  The right-hand-side tiles y' run in k_reduce_big.
-template <class T, class TI = T>
+template <class T, class EI = cx<T>, bool RE = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_reduce_lds(const Seg* __restrict__ segs, int nseg,
                                                     int64_t total, int ntile,
-                                                    const cx<TI>* __restrict__ inA,
+                                                    const EI* __restrict__ inA,
                                                     cx<T>* __restrict__ W,
                                                     const unsigned long long* __restrict__ flags)
 {
@@ -948,7 +953,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         sB[b][o_ + 8 * LD] = rb2;                                                                   \
         sB[b][o_ + 12 * LD] = rb3;                                                                  \
     } while (0)
-    Acc3<T, 2, 2> acc;
+    Acc3<T, 2, 2, RE> acc;
     acc.zero();
     if (npan > 0) {
         CRS_PANEL_LOAD(0);
@@ -980,8 +985,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
                         acc.t1[i][j] = MF<T>::mma(ar[i], br[j], acc.t1[i][j]);
-                        acc.t2[i][j] = MF<T>::mma(ai[i], bi[j], acc.t2[i][j]);
-                        acc.t3[i][j] = MF<T>::mma(as[i], bs[j], acc.t3[i][j]);
+                        if constexpr (!RE) {
+                            acc.t2[i][j] = MF<T>::mma(ai[i], bi[j], acc.t2[i][j]);
+                            acc.t3[i][j] = MF<T>::mma(as[i], bs[j], acc.t3[i][j]);
+                        }
                     }
             }
         }
@@ -993,7 +1000,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 #undef CRS_PANEL_STORE
     const int ib = i0 + 32 * wa, jb = j0 + 32 * wb;
     if (kind == 0) {
-        const cx<TI>* Aq = inA + s.oA + q * mm;
+        const EI* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -1037,7 +1044,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 //     publishes it in LDS; every wave J < I then applies
 //     w_J -= L_IJ^H x_I (its operand loaded one step ahead).
 // The block's serial chain is S short steps instead of S full tile sweeps.
-template <class T>
+template <class T, bool RE = false>
 __global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int nstrip,
                                                    const cx<T>* __restrict__ W,
@@ -1099,14 +1106,14 @@ __global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs,
     for (int v = 0; v < 4; ++v)
         aD[v] = own ? Dg[wv * 256 + MF<T>::row(kr, v) * 16 + cc] : czero<T>();
     // phase A
-    Acc3<T, 1, 1> acc;
+    Acc3<T, 1, 1, RE> acc;
     acc.zero();
     if (own && hasPrev)
-        wave_mm3<T, 1, 1, false, false, 4>(acc, WOp<T>{Q + (int64_t)r0 * m, m, 1, m - r0},
-                                           WOp<T>{xm + c0, 1, k, nc}, m);
+        wave_mm3<T, 1, 1, false, false, 4, RE>(acc, WOp<T>{Q + (int64_t)r0 * m, m, 1, m - r0},
+                                               WOp<T>{xm + c0, 1, k, nc}, m);
     if (own && hasNext)
-        wave_mm3<T, 1, 1, false, false, 4>(acc, WOp<T>{P + (int64_t)r0 * m, m, 1, m - r0},
-                                           WOp<T>{xn + c0, 1, k, nc}, m);
+        wave_mm3<T, 1, 1, false, false, 4, RE>(acc, WOp<T>{P + (int64_t)r0 * m, m, 1, m - r0},
+                                               WOp<T>{xn + c0, 1, k, nc}, m);
     v4 wr, wi;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1140,9 +1147,11 @@ __global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs,
             for (int v = 0; v < 4; ++v) {
                 const cx<T> q = aD[v];
                 xr = MF<T>::mma(q.r, wr[v], xr);
-                xr = MF<T>::mma(q.i, wi[v], xr);
-                xi = MF<T>::mma(q.r, wi[v], xi);
-                xi = MF<T>::mma(-q.i, wr[v], xi);
+                if constexpr (!RE) {
+                    xr = MF<T>::mma(q.i, wi[v], xr);
+                    xi = MF<T>::mma(q.r, wi[v], xi);
+                    xi = MF<T>::mma(-q.i, wr[v], xi);
+                }
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -1160,9 +1169,11 @@ __global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs,
                 const cx<T> b = sx[(4 * q + kr) * 16 + cc];
                 const T ar = a[q].r, ai = -a[q].i; // conj(L)
                 wr = MF<T>::mma(-ar, b.r, wr);
-                wr = MF<T>::mma(ai, b.i, wr);
-                wi = MF<T>::mma(-ar, b.i, wi);
-                wi = MF<T>::mma(-ai, b.r, wi);
+                if constexpr (!RE) {
+                    wr = MF<T>::mma(ai, b.i, wr);
+                    wi = MF<T>::mma(-ar, b.i, wi);
+                    wi = MF<T>::mma(-ai, b.r, wi);
+                }
             }
         }
         __syncthreads();

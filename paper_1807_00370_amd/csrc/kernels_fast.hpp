@@ -114,22 +114,47 @@ constexpr int kGroup = 4;
 // componentwise; Higham, Accuracy and Stability of Numerical Algorithms,
 // Section 23.2.4).  For real data t2 = 0 and t3 = t1 bit for bit, so the
 // imaginary part is exactly zero.
-template <class T, int RM, int RN>
+//
+// RE (real data: every imaginary part is zero): only t1 is formed, one real
+// MFMA per contraction step, Re = t1 and Im = 0 -- the same values the 3M
+// form gives for real data (t2 = 0, t3 = t1), with a third of the MFMAs.
+template <class T, int RM, int RN, bool RE = false>
 struct Acc3 {
     using v4 = typename MF<T>::v4;
-    v4 t1[RM][RN], t2[RM][RN], t3[RM][RN];
+    v4 t1[RM][RN], t2[RE ? 1 : RM][RE ? 1 : RN], t3[RE ? 1 : RM][RE ? 1 : RN];
     __device__ __forceinline__ void zero()
     {
 #pragma unroll
         for (int i = 0; i < RM; ++i)
 #pragma unroll
-            for (int j = 0; j < RN; ++j)
-                t1[i][j] = t2[i][j] = t3[i][j] = v4{0, 0, 0, 0};
+            for (int j = 0; j < RN; ++j) {
+                t1[i][j] = v4{0, 0, 0, 0};
+                if constexpr (!RE)
+                    t2[i][j] = t3[i][j] = v4{0, 0, 0, 0};
+            }
     }
-    __device__ __forceinline__ T re(int i, int j, int v) const { return t1[i][j][v] - t2[i][j][v]; }
+    __device__ __forceinline__ T re(int i, int j, int v) const
+    {
+        if constexpr (RE)
+            return t1[i][j][v];
+        else
+            return t1[i][j][v] - t2[i][j][v];
+    }
     __device__ __forceinline__ T im(int i, int j, int v) const
     {
-        return t3[i][j][v] - t1[i][j][v] - t2[i][j][v];
+        if constexpr (RE)
+            return T(0);
+        else
+            return t3[i][j][v] - t1[i][j][v] - t2[i][j][v];
+    }
+    // acc(i, j) += a b for one contraction step of real-pair operands
+    __device__ __forceinline__ void step(int i, int j, T ar, T ai, T br, T bi)
+    {
+        t1[i][j] = MF<T>::mma(ar, br, t1[i][j]);
+        if constexpr (!RE) {
+            t2[i][j] = MF<T>::mma(ai, bi, t2[i][j]);
+            t3[i][j] = MF<T>::mma(ar + ai, br + bi, t3[i][j]);
+        }
     }
 };
 
@@ -256,11 +281,11 @@ __device__ __forceinline__ void tile_nn3(Acc3<T, 1, 1>& acc, const cx<T>* __rest
 
 // ----------------------------------------------------------------- k_elim_w
 
-template <class T, int MT, class TI = T>
+template <class T, int MT, class EI = cx<T>>
 __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* __restrict__ segs, int nseg,
-                                               int64_t total, const cx<TI>* __restrict__ inA,
-                                               const cx<TI>* __restrict__ inB,
-                                               const cx<TI>* __restrict__ iny,
+                                               int64_t total, const EI* __restrict__ inA,
+                                               const EI* __restrict__ inB,
+                                               const EI* __restrict__ iny,
                                                cx<T>* __restrict__ W,
                                                unsigned long long* __restrict__ flags,
                                                int with_mat, int with_rhs)
@@ -291,7 +316,7 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
         cx<T>* Lg = W + s.oL + t * mm;
         __syncthreads();
         if (with_mat) {
-            const cx<TI>* Ap = inA + s.oA + (int64_t)p * mm;
+            const EI* Ap = inA + s.oA + (int64_t)p * mm;
             for (int e = lane; e < np; e += 64) {
                 const int r = tri_row(e), c = e - r * (r + 1) / 2;
                 sL[e] = cvt<T>(Ap[r * m + c]);
@@ -358,9 +383,9 @@ __global__ __launch_bounds__(64, (col_waves<T, MT>())) void k_elim_w(const Seg* 
         const int nQ = (with_mat && hasPrev) ? m : 0;
         const int nY = with_rhs ? k : 0;
         const int ncol = nP + nQ + nY;
-        const cx<TI>* Bp = inB + s.oB + (int64_t)p * mm;
-        const cx<TI>* Bq = inB + s.oB + (int64_t)(p - d) * mm;
-        const cx<TI>* yp = iny + s.oy + (int64_t)p * mk;
+        const EI* Bp = inB + s.oB + (int64_t)p * mm;
+        const EI* Bq = inB + s.oB + (int64_t)(p - d) * mm;
+        const EI* yp = iny + s.oy + (int64_t)p * mk;
         for (int vc0 = 0; vc0 < ncol; vc0 += 64) {
             const int vc = vc0 + lane;
             const bool act = vc < ncol;
@@ -486,12 +511,12 @@ __device__ __forceinline__ void inverse_tiles_lds(cx<T>* sL, int m)
 // no cross-wave synchronisation); wave 0 alone stores L and raises the
 // breakdown flag.  Levels with few blocks use nsplit > 1 to shorten the
 // chain of strips that one wave walks through.
-template <class T, int MT, class TI = T>
+template <class T, int MT, class EI = cx<T>>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_elim_mf(const Seg* __restrict__ segs, int nseg,
                                                    int64_t total, int nsplit,
-                                                   const cx<TI>* __restrict__ inA,
-                                                   const cx<TI>* __restrict__ inB,
-                                                   const cx<TI>* __restrict__ iny,
+                                                   const EI* __restrict__ inA,
+                                                   const EI* __restrict__ inB,
+                                                   const EI* __restrict__ iny,
                                                    cx<T>* __restrict__ W,
                                                    unsigned long long* __restrict__ flags,
                                                    int with_mat, int with_rhs)
@@ -523,20 +548,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     const int nP = (with_mat && hasNext) ? S : 0;
     const int nQ = (with_mat && hasPrev) ? S : 0;
     const int nst = nP + nQ + (with_rhs ? (k + 15) / 16 : 0);
-    const cx<TI>* Bp = inB + s.oB + (int64_t)p * mm;
-    const cx<TI>* Bq = inB + s.oB + (int64_t)(p - d) * mm;
-    const cx<TI>* yp = iny + s.oy + (int64_t)p * mk;
+    const EI* Bp = inB + s.oB + (int64_t)p * mm;
+    const EI* Bq = inB + s.oB + (int64_t)(p - d) * mm;
+    const EI* yp = iny + s.oy + (int64_t)p * mk;
     // element (r, c) of strip st's source is base[r * sr + c * sc], conjugated
     // for B_p^H
 #define CRS_LOAD_STRIP(st, g)                                                                      \
     do {                                                                                           \
         const int src_ = (st) < nP ? 0 : ((st) < nP + nQ ? 1 : 2);                                 \
         const int c_ = 16 * (src_ == 0 ? (st) : (src_ == 1 ? (st) - nP : (st) - nP - nQ)) + cc;    \
-        const cx<TI>* base_ = src_ == 0 ? Bp : (src_ == 1 ? Bq : yp);                              \
+        const EI* base_ = src_ == 0 ? Bp : (src_ == 1 ? Bq : yp);                              \
         const int sr_ = src_ == 0 ? 1 : (src_ == 1 ? m : k), sc_ = src_ == 0 ? m : 1;               \
         const bool okc_ = c_ < (src_ == 2 ? k : m);                                                \
         const T cj_ = src_ == 0 ? T(-1) : T(1);                                                    \
-        const cx<TI>* col_ = base_ + (okc_ ? c_ : 0) * sc_;                                        \
+        const EI* col_ = base_ + (okc_ ? c_ : 0) * sc_;                                        \
         _Pragma("unroll") for (int I_ = 0; I_ < S; ++I_)                                           \
             _Pragma("unroll") for (int v_ = 0; v_ < 4; ++v_)                                       \
             {                                                                                      \
@@ -550,7 +575,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     cx<T> gn[S][4];
 
     if (with_mat) {
-        const cx<TI>* Ap = inA + s.oA + (int64_t)p * mm;
+        const EI* Ap = inA + s.oA + (int64_t)p * mm;
         for (int e = lane; e < np; e += 64) {
             const int r = tri_row(e), c = e - r * (r + 1) / 2;
             sL[e] = cvt<T>(Ap[r * m + c]);
@@ -765,10 +790,10 @@ __device__ __forceinline__ void mma_hn3(Acc3<T, 1, 1>& acc, const OpTile<T, KS>&
 //   y'_q = y_q - P_l^H g_l - Q_r^H g_r.
 // Each 16-column operand tile is loaded from memory once and reused by every
 // output tile that needs it (NT16 = MT / 16 tiles per m x m operand).
-template <class T, int MT, class TI = T>
+template <class T, int MT, class EI = cx<T>>
 __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs, int nseg,
-                                                    int64_t total, const cx<TI>* __restrict__ inA,
-                                                    const cx<TI>* __restrict__ iny,
+                                                    int64_t total, const EI* __restrict__ inA,
+                                                    const EI* __restrict__ iny,
                                                     cx<T>* __restrict__ W,
                                                     const unsigned long long* __restrict__ flags,
                                                     int with_mat, int with_rhs)
@@ -837,7 +862,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
         }
     }
     if (with_mat) {
-        const cx<TI>* Aq = inA + s.oA + q * mm;
+        const EI* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll
         for (int i = 0, v = 0; i < NT16; ++i)
@@ -856,7 +881,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
                 }
     }
     if (kc0) {
-        const cx<TI>* yq = iny + s.oy + q * mk;
+        const EI* yq = iny + s.oy + q * mk;
         cx<T>* yo = W + s.oyo + oi * mk;
 #pragma unroll
         for (int i = 0; i < NT16; ++i)
@@ -893,7 +918,7 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
     }
     // remaining right-hand-side chunks (k > 16)
     if (with_rhs && k > 16) {
-        const cx<TI>* yq = iny + s.oy + q * mk;
+        const EI* yq = iny + s.oy + q * mk;
         cx<T>* yo = W + s.oyo + oi * mk;
         for (int c0 = 16; c0 < k; c0 += 16) {
 #pragma unroll
@@ -927,10 +952,10 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
 
 // --------------------------------------------------------------- k_reduce_t
 
-template <class T, int MT, class TI = T>
+template <class T, int MT, class EI = cx<T>>
 __global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* __restrict__ segs, int nseg,
-                                                 int64_t total, const cx<TI>* __restrict__ inA,
-                                                 const cx<TI>* __restrict__ iny,
+                                                 int64_t total, const EI* __restrict__ inA,
+                                                 const EI* __restrict__ iny,
                                                  cx<T>* __restrict__ W,
                                                  const unsigned long long* __restrict__ flags,
                                                  int with_mat, int with_rhs)
@@ -958,7 +983,7 @@ __global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* 
         const cx<T>* Qr = W + s.oQ + tr * mm;
         const cx<T>* Pr = W + s.oP + tr * mm;
         if (with_mat) {
-            const cx<TI>* Aq = inA + s.oA + q * mm;
+            const EI* Aq = inA + s.oA + q * mm;
             cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll 1
             for (int ti = 0; ti < NT16; ++ti) {
@@ -1009,7 +1034,7 @@ __global__ __launch_bounds__(64, (MT >= 64 ? 2 : 4)) void k_reduce_t(const Seg* 
         if (with_rhs) {
             const cx<T>* gl = W + s.og + tl * mk;
             const cx<T>* gr = W + s.og + tr * mk;
-            const cx<TI>* yq = iny + s.oy + q * mk;
+            const EI* yq = iny + s.oy + q * mk;
             cx<T>* vo = W + s.oyo + oi * mk;
 #pragma unroll 1
             for (int ti = 0; ti < NT16; ++ti) {

@@ -15,7 +15,8 @@ import torch
 
 from . import _lib
 
-_DT = {torch.complex128: _lib.C128, torch.complex64: _lib.C64}
+_DT = {torch.complex128: _lib.C128, torch.complex64: _lib.C64, torch.float64: _lib.R64,
+       torch.float32: _lib.R32}
 PCR_TAIL_DEFAULT = 64
 _PREC = {"native": _lib.PREC_NATIVE, "fp32_refine": _lib.PREC_FP32_REFINE}
 _SCHED = {"cr": _lib.SCHED_CR, "pcr": _lib.SCHED_PCR}

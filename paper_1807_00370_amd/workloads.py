@@ -130,20 +130,51 @@ def random_hpd(N: int, m: int, k: int, seed: int, *, margin: float = 1.0,
                                    diag_shift=diag_shift))
 
 
-def poisson(N: int, m: int, p: int = 1, q: int = 1) -> System:
+def random_spd(N: int, m: int, k: int, seed: int, *, margin: float = 1.0,
+               shift_scale: float = 0.0) -> System:
+    """The real case of the generator: ``B_j`` iid normal with standard
+    deviation ``1/sqrt(m)``, ``A_j = M_j M_j^T / m + (||B_{j-1}||_2 +
+    ||B_j||_2 + margin) I``, ``y`` iid normal; real float64 arrays.
+    ``shift_scale`` as in ``random_hpd``.  Draw order B, M, y."""
+    if N < 1 or m < 1 or k < 1:
+        raise ValueError("N, m, k must be >= 1")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B = rng.standard_normal((max(N - 1, 0), m, m)) / math.sqrt(m)
+    nb = spectral_norms(B.astype(np.complex128)) if N > 1 else np.zeros(0)
+    left = np.zeros(N)
+    right = np.zeros(N)
+    if N > 1:
+        left[1:] = nb
+        right[:-1] = nb
+    diag = left + right + margin
+    if shift_scale:
+        diag = diag - shift_scale * (left + right + margin)
+    M = rng.standard_normal((N, m, m))
+    A = M @ np.swapaxes(M, 1, 2) / m
+    A = 0.5 * (A + np.swapaxes(A, 1, 2))
+    idx = np.arange(m)
+    A[:, idx, idx] += diag[:, None]
+    y = rng.standard_normal((N, m, k))
+    return System(np.ascontiguousarray(A), np.ascontiguousarray(B), y, None,
+                  dict(kind="random_spd", N=N, m=m, k=k, seed=seed, margin=margin,
+                       shift_scale=shift_scale))
+
+
+def poisson(N: int, m: int, p: int = 1, q: int = 1, real: bool = False) -> System:
     """Block 2D Poisson system with an eigenvector right-hand side (k = 1).
 
     Returns the eigenvalue as ``meta['lam']``; the exact solution is
-    ``y / lam``.
+    ``y / lam``.  ``real``: float64 arrays instead of complex128.
     """
+    dt = np.float64 if real else np.complex128
     A1 = 4.0 * np.eye(m) - np.eye(m, k=1) - np.eye(m, k=-1)
-    A = np.broadcast_to(A1, (N, m, m)).astype(np.complex128)
-    B = np.broadcast_to(-np.eye(m), (max(N - 1, 0), m, m)).astype(np.complex128)
+    A = np.broadcast_to(A1, (N, m, m)).astype(dt)
+    B = np.broadcast_to(-np.eye(m), (max(N - 1, 0), m, m)).astype(dt)
     a = np.arange(1, m + 1)
     j = np.arange(1, N + 1)
     ya = np.sin(p * a * math.pi / (m + 1))
     yj = np.sin(q * j * math.pi / (N + 1))
-    y = (yj[:, None] * ya[None, :])[:, :, None].astype(np.complex128)
+    y = (yj[:, None] * ya[None, :])[:, :, None].astype(dt)
     lam = 4.0 - 2.0 * math.cos(p * math.pi / (m + 1)) - 2.0 * math.cos(q * math.pi / (N + 1))
     return System(np.ascontiguousarray(A), np.ascontiguousarray(B), y, None,
                   dict(kind="poisson", N=N, m=m, k=1, p=p, q=q, lam=lam))

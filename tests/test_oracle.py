@@ -412,3 +412,19 @@ def test_hybrid_flag_scalar_golden(H):
     x, info = oracle.solve_hybrid(A, B, y, H)
     assert info == dict(status=1, level=2, block=4)
     assert np.isnan(x).all()
+
+
+def test_real_generator_and_real_solution():
+    """The real case (Section 1 with real blocks): the real generator gives a
+    symmetric positive definite matrix, and the oracle's solution of a real
+    system is real (zero imaginary parts) and equals numpy's dense real
+    solve."""
+    s = W.random_spd(40, 5, 3, 2024)
+    assert s.A.dtype == np.float64 and np.array_equal(s.A, np.swapaxes(s.A, 1, 2))
+    D = dense(s.A, s.B).real
+    assert np.linalg.eigvalsh(D)[0] > 0
+    x, info = oracle.solve_cr(s.A, s.B, s.y)
+    assert info["status"] == 0
+    assert np.all(x.imag == 0.0)
+    xd = np.linalg.solve(D, stack(s.y)).reshape(s.y.shape)
+    assert rel_err(x.real, xd) < 1e-12
