@@ -144,14 +144,19 @@ def add(a, b, scale=1.0):
     return a
 
 
-def step_model(form, N, m, k, iters=0):
+def step_model(form, N, m, k, iters=0, real=False):
     """Per-kernel algorithmic [bytes, flops] of one step of a form.  The mixed
     form: the fused factor + first solve (level 0 reads the FP64 A, B, y and
     assigns x), `iters` correction passes (level 0 reads the FP64 residual
     and adds to x), and one FP64 residual per solve (read A_j lower, B_j,
     x_j, y_j; write r_j in FP64)."""
     if form == "fp64":
-        return pass_model(N, m, k, lambda n: 16, True, True)
+        tot = pass_model(N, m, k, lambda n: 16, True, True, s_in0=8 if real else None)
+        if real:
+            # real data: a real multiply-add (2 flops) per complex one (8)
+            for v in tot.values():
+                v[1] /= 4.0
+        return tot
     s_lvl = lambda n: 16 if n <= TAIL else 8
     tot = {}
     add(tot, pass_model(N, m, k, s_lvl, True, True, s_in0=16, upd=1))
@@ -626,7 +631,8 @@ def main():
     ap.add_argument("--N", type=int, default=65536)
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--k", type=int, default=16)
-    ap.add_argument("--forms", default="fp64,fp64_onesided,fp32_refine")
+    ap.add_argument("--forms", default=None,
+                    help="default: fp64,fp64_onesided,fp32_refine (poisson: fp64,r64,fp32_refine)")
     ap.add_argument("--schedule", choices=("cr", "pcr"), default="cr",
                     help="cr: one-sided reduction (default); pcr: Algorithm 1 as printed (fp64)")
     ap.add_argument("--batch-half-max", type=int, default=4096,
@@ -647,6 +653,9 @@ def main():
                     help="one plain device copy of A (known size) before timing, to calibrate "
                          "HBM byte counters")
     args = ap.parse_args()
+    if args.forms is None:
+        args.forms = ("fp64,r64,fp32_refine" if args.workload == "poisson"
+                      else "fp64,fp64_onesided,fp32_refine")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs each system on a single "
               "device and this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -690,7 +699,13 @@ def main():
     pcr = args.schedule == "pcr"
 
     def run_form(form, s, A, B, y, x, rtol, steps, warmup, tag):
-        if form in ("fp64", "fp64_onesided"):
+        if form == "r64":
+            # the real symmetric dtype on the real arrays of the same system
+            A, B, y = (t.real.contiguous() for t in (A, B, y))
+            x = torch.empty_like(y)
+            s = W.System(s.A.real.copy(), s.B.real.copy(), s.y.real.copy(), None, s.meta)
+            sol = Solver([s.N], [s.m], [s.k], dtype=torch.float64, device=dev)
+        elif form in ("fp64", "fp64_onesided"):
             # fp64: one-sided levels, then Algorithm 1 below 64 blocks (the
             # library default); fp64_onesided: one-sided throughout
             sol = Solver([s.N], [s.m], [s.k], dtype=torch.complex128, device=dev,
@@ -706,10 +721,15 @@ def main():
         info = sol.info_host()[0]
         if info["status"] != 0:
             raise SystemExit("%s: factorization failed: %s" % (tag, info))
-        rel = sol.residual(A, B, x, y)[0]
+        if form == "r64":  # no device residual for the real dtypes: the oracle's
+            import oracle
+            rel = oracle.rel_residual(s.A, s.B, x.cpu().numpy(), s.y)
+        else:
+            rel = sol.residual(A, B, x, y)[0]
         iters = int(info["refine_iters"]) if form == "fp32_refine" else 0
         mod = pcr_model(s.N, s.m, s.k) if pcr else step_model(
-            "fp64" if form != "fp32_refine" else form, s.N, s.m, s.k, iters)
+            "fp64" if form != "fp32_refine" else form, s.N, s.m, s.k, iters,
+            real=form == "r64")
         rec = {
             "pcr_tail_blocks": sol.pcr_tail_blocks,
             "ms_per_step": ms,
@@ -822,7 +842,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64+f64" if best == "fp32_refine" else "c128",
+        "dtype": {"fp32_refine": "c64+f64", "r64": "f64"}.get(best, "c128"),
         "data": "synthetic",
         "config": {"workload": "%s, N=%d block rows, m=%d, k=%d, complex128 inputs, solved "
                                "to rel. residual <= %.3g (%s, %s form)" % (
