@@ -259,10 +259,15 @@ int crsolve_set_graphs(crsolve_plan *plan, int enable);
  * one elimination and one back-substitution kernel (tiled) and two variants
  * of the reduced-system formation (16 x 16 tiles, or one wave per block), so
  * only that role is tuned for them; blocks above 64 have one kernel per role
- * and are not tuned.  The choice is returned as a short text (cap
- * bytes, NUL-terminated), one token "r<role>c<class>f<fp64>=<variant>;" per
- * tuned role, that crsolve_set_tuning applies to another plan, e.g. from a
- * cache file.  NATIVE plans only. */
+ * and are not tuned.  When blocks of 9..32 are present it also times whole
+ * steps for the launch shapes of their few-block levels -- the waves a level
+ * splits its eliminations over (1024, 2048, 4096) and the block count below
+ * which a reduced system is formed one wave per 16 x 16 tile (512, 1024,
+ * 2048) -- and keeps the fastest pair.  The choice is returned as a short
+ * text (cap bytes, NUL-terminated), one token
+ * "r<role>c<class>f<fp64>=<variant>;" per tuned role plus "tw=<waves>;" and
+ * "tb=<blocks>;", that crsolve_set_tuning applies to another plan, e.g. from
+ * a cache file.  NATIVE plans only. */
 int crsolve_autotune(crsolve_plan *plan, const void *A, const void *B, const void *y, void *ws,
                      size_t ws_bytes, void *x, void *stream, char *choice, size_t cap);
 int crsolve_set_tuning(crsolve_plan *plan, const char *choice);

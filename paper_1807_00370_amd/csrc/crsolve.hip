@@ -186,6 +186,10 @@ struct crsolve_plan {
     // kernel variant per (role: elim, reduce, back; class; precision):
     // 0 = one-wave / MFMA kernels, 1 = work-group kernels (autotuner)
     int var[3][kNumCls][2] = {};
+    // launch shapes of the levels with few blocks (autotuner): waves per
+    // level for the split elimination, block count below which the reduced
+    // system is formed one wave per 16 x 16 tile
+    int64_t tail_waves = 2048, tail_blocks = 1024;
 
     // recorded HIP graphs (crsolve_set_graphs)
     struct GraphEntry {
@@ -399,13 +403,11 @@ unsigned grid8(int64_t items) { return (unsigned)((items + 7) / 8 * 8); }
 
 // Levels of the one-wave MFMA classes (8 < m <= 32) with few blocks are bound
 // by one block's chain of dependent steps, not by throughput.  There the
-// elimination splits each block's strips over up to kTailWaves / blocks
-// waves, and launches of at most kTailBlocks blocks form the reduced system
-// one wave per 16 x 16 output tile.  Both thresholds were measured on the
-// N = 65536, m = 32 workload (kTailWaves 1024 .. 8192, kTailBlocks 512 ..
-// 4096); kTailWaves is about the wave slots of the GPU's 1024 SIMDs.
-constexpr int64_t kTailWaves = 2048;
-constexpr int64_t kTailBlocks = 1024;
+// elimination splits each block's strips over up to tail_waves / blocks
+// waves, and launches of at most tail_blocks blocks form the reduced system
+// one wave per 16 x 16 output tile.  Defaults 2048 and 1024 (measured on the
+// N = 65536, m = 32 workload; 2048 is about the wave slots of the GPU's 1024
+// SIMDs); the autotuner picks both per plan.
 
 bool mf_class(int cls) { return cls == 2 || cls == 3; }
 
@@ -454,7 +456,7 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
     if (mf_class(L.cls) && v == 0) {
         const BigDims b = big_dims(c.p, L);
         const int nst = (mat ? 2 * b.S : 0) + (rhs ? b.K16 : 0);
-        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nst, kTailWaves / L.total));
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nst, c.p->tail_waves / L.total));
     }
 #define CALL(MT) Disp<T, EI, RE>::template elim<MT>(L, c.dsegs, inA, inB, iny, c.ws, c.flags, mat, rhs, c.st, v, nsplit)
     CRS_BY_CLASS(L.cls, CALL)
@@ -506,7 +508,7 @@ void run_reduce(const Ctx& c, const Launch& L, const void* A, const void* y, int
                                (const EI*)iny, (cx<T>*)c.ws, c.flags);
         return;
     }
-    if (mf_class(L.cls) && L.total <= kTailBlocks) {
+    if (mf_class(L.cls) && L.total <= c.p->tail_blocks) {
         const BigDims b = big_dims(c.p, L);
         const int nt = (mat ? b.S * (b.S + 1) / 2 + b.S * b.S : 0) + (rhs ? b.S * b.K16 : 0);
         if (nt > 0)
@@ -1825,10 +1827,28 @@ int crsolve_set_tuning(crsolve_plan* p, const char* choice)
 {
     if (!p || !choice)
         return CRSOLVE_EINVAL;
-    // tokens "r<role>c<class>f<precision>=<variant>;"
+    // tokens "r<role>c<class>f<precision>=<variant>;", "tw=<waves>;",
+    // "tb=<blocks>;"
     const char* q = choice;
     while (*q) {
         int r, c, f, v, n = 0;
+        long long lv = 0;
+        if (std::sscanf(q, "tw=%lld;%n", &lv, &n) == 1 && n > 0) {
+            if (lv < 1 || lv > (1ll << 20))
+                return CRSOLVE_EINVAL;
+            p->tail_waves = lv;
+            q += n;
+            continue;
+        }
+        n = 0;
+        if (std::sscanf(q, "tb=%lld;%n", &lv, &n) == 1 && n > 0) {
+            if (lv < 0 || lv > (1ll << 30))
+                return CRSOLVE_EINVAL;
+            p->tail_blocks = lv;
+            q += n;
+            continue;
+        }
+        n = 0;
         if (std::sscanf(q, "r%dc%df%d=%d;%n", &r, &c, &f, &v, &n) != 4 || n == 0)
             return CRSOLVE_EINVAL;
         if (r < 0 || r > 2 || c < 0 || c >= kNumCls || f < 0 || f > 1 || v < 0 || v > 1)
@@ -1899,6 +1919,53 @@ int crsolve_autotune(crsolve_plan* p, const void* A, const void* B, const void* 
                     out += "r" + std::to_string(r) + "c" + std::to_string(c) + "f" +
                            std::to_string(f) + "=" + std::to_string(v) + ";";
             }
+    // launch shapes of the few-block levels of the one-wave MFMA classes:
+    // whole steps timed for each pair, the fastest kept
+    bool mf = false;
+    for (int s = 0; s < p->batch; ++s)
+        mf |= mf_class(p->cls[s]);
+    if (mf) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return CRSOLVE_EHIP;
+        const int64_t cw[3] = {1024, 2048, 4096}, cb[3] = {512, 1024, 2048};
+        float best = 0.f;
+        int64_t bw = p->tail_waves, bb = p->tail_blocks;
+        Ctx c = make_ctx(p, ws, st);
+        for (int i = 0; i < 3 && rc == CRSOLVE_OK; ++i)
+            for (int j = 0; j < 3 && rc == CRSOLVE_OK; ++j) {
+                p->tail_waves = cw[i];
+                p->tail_blocks = cb[j];
+                float tmin = 0.f;
+                for (int rep = 0; rep < 3; ++rep) {
+                    if ((rc = upload(p, c.ws, st)))
+                        break;
+                    (void)hipEventRecord(e0, st);
+                    enqueue_native_fs(c, A, B, y, x, nullptr);
+                    (void)hipEventRecord(e1, st);
+                    float ms = 0.f;
+                    if (hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        rc = CRSOLVE_EHIP;
+                        break;
+                    }
+                    if (rep > 0 && (rep == 1 || ms < tmin))
+                        tmin = ms;
+                }
+                if (rc == CRSOLVE_OK && (best == 0.f || tmin < best)) {
+                    best = tmin;
+                    bw = cw[i];
+                    bb = cb[j];
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc)
+            return rc;
+        p->tail_waves = bw;
+        p->tail_blocks = bb;
+        out += "tw=" + std::to_string(bw) + ";tb=" + std::to_string(bb) + ";";
+    }
     p->drop_graphs();
     p->graphs_on = graphs;
     p->mark_factored(ws);

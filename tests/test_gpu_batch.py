@@ -112,10 +112,20 @@ def test_autotune_choice_and_both_variants(tdev):
     toks = choice.strip(";").split(";")
     classes = {0 if m <= 4 else 1 if m <= 8 else 2 if m <= 16 else 3 if m <= 32 else 4
                for m in s.ms}
+    # launch shapes of the few-block levels (blocks of 9..32 are present)
+    shape = [t for t in toks if t.startswith("tw=") or t.startswith("tb=")]
+    assert len(shape) == 2 and re.fullmatch(r"tw=(1024|2048|4096)", shape[0]) and \
+        re.fullmatch(r"tb=(512|1024|2048)", shape[1]), shape
+    toks = [t for t in toks if t not in shape]
     # blocks above 32 (class 4) tune only the reduced-system role
     assert len(toks) == sum(1 if c >= 4 else 3 for c in classes)
     for t in toks:
         assert re.fullmatch(r"r[0-2]c[0-4]f1=[01]", t), t
+    # the choice applies to another plan of the same batch
+    s2 = _solver(torch, dev, systems)
+    s2.plan.set_tuning(choice)
+    x2 = s2.factor_solve(At, Bt, yt).cpu().numpy()
+    _check_all(systems, _split(x2, systems))
     x = s.factor_solve(At, Bt, yt).cpu().numpy()
     _check_all(systems, _split(x, systems))
     for v in (0, 1):
