@@ -44,7 +44,8 @@ Profiling runs add --no-autotune (default kernel variants), --calib-copy
 (a device copy of A of known size for counter calibration) and
 --no-box-peaks.  After the timed steps the roofline entry also reports the
 GPU's achievable peaks measured with library kernels (peak_measured: a 1 GiB
-device copy, 8192^3 FP64 / FP32 GEMMs) and the fraction of those.
+device copy, 8192^3 FP64 / FP32 GEMMs) and the fraction of those, with the
+one-directional HBM rates (a 1 GiB reduction and fill) beside the copy's.
 """
 from __future__ import annotations
 
@@ -412,8 +413,14 @@ def box_peaks():
 
     a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
-    _BOX["hbm_GBs"] = 2 * a.numel() * 8 / timed(lambda: b.copy_(a), 10) / 1e9
-    del a, b
+    nb = a.numel() * 8
+    _BOX["hbm_GBs"] = 2 * nb / timed(lambda: b.copy_(a), 10) / 1e9
+    # one-directional rates beside the copy's mixed one (a reduction reads,
+    # a fill writes)
+    s = torch.empty((), dtype=torch.float64, device=dev)
+    _BOX["hbm_read_GBs"] = nb / timed(lambda: torch.sum(a, dim=0, out=s), 10) / 1e9
+    _BOX["hbm_write_GBs"] = nb / timed(lambda: b.fill_(2.0), 10) / 1e9
+    del a, b, s
     M = 8192
     for dt, key in ((torch.float64, "fp64_TFs"), (torch.float32, "fp32_TFs")):
         g = torch.Generator(device=dev)
@@ -437,6 +444,9 @@ def add_measured_peak(roof):
     roof["frac_of_measured"] = roof["achieved"] / ref
     roof["peak_measured_how"] = ("1 GiB device copy, read + written bytes" if roof["unit"] == "GB/s"
                                  else "8192^3 GEMM through torch.matmul")
+    if roof["unit"] == "GB/s":
+        roof["peak_measured_read"] = pk["hbm_read_GBs"]
+        roof["peak_measured_write"] = pk["hbm_write_GBs"]
 
 
 def emit(args, value, ms, dtype, config, forms, roof, cpu, model=None):

@@ -216,16 +216,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     } else {
         const int c0 = 16 * item, cw = min(16, k - c0);
         constexpr int G = RM >= 2 ? 2 : 4;
+        // B_j is read by rows j (as B_j^H) and j + 1 (as B_j), which run
+        // side by side on one XCD: an even row takes its products in the
+        // order B_{j-1}, A_j, B_j^H and an odd row in the reverse order, so
+        // both readers of a B_j fetch it at the same phase of their lives and
+        // the second read finds it in L2.
+        const bool odd = j & 1;
         for (int r0 = 0; r0 < m; r0 += 16 * RM) {
             v4 cr[RM][1], ci[RM][1];
             zero_acc<T, RM, 1>(cr, ci);
-            if (j > 0) // B_{j-1} x_{j-1}
-                wave_mm<T, RM, 1, false, false, G>(cr, ci, WOp<T>{Bm + (int64_t)r0 * m, m, 1, m - r0},
-                                                   WOp<T>{xj - mk + c0, 1, k, cw}, m);
+            auto prev = [&] { // B_{j-1} x_{j-1}
+                if (j > 0)
+                    wave_mm<T, RM, 1, false, false, G>(cr, ci, WOp<T>{Bm + (int64_t)r0 * m, m, 1, m - r0},
+                                                       WOp<T>{xj - mk + c0, 1, k, cw}, m);
+            };
+            auto next = [&] { // B_j^H x_{j+1}
+                if (j + 1 < n)
+                    wave_mm<T, RM, 1, true, false, G>(cr, ci, WOp<T>{Bj + r0, 1, m, m - r0},
+                                                      WOp<T>{xj + mk + c0, 1, k, cw}, m);
+            };
+            if (odd)
+                next();
+            else
+                prev();
             wave_mm_herm_r<T, RM, G>(cr, ci, Aj, m, r0, WOp<T>{xj + c0, 1, k, cw});
-            if (j + 1 < n) // B_j^H x_{j+1}
-                wave_mm<T, RM, 1, true, false, G>(cr, ci, WOp<T>{Bj + r0, 1, m, m - r0},
-                                                  WOp<T>{xj + mk + c0, 1, k, cw}, m);
+            if (odd)
+                prev();
+            else
+                next();
 #pragma unroll
             for (int a = 0; a < RM; ++a)
 #pragma unroll
