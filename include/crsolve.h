@@ -130,7 +130,9 @@ typedef struct {
                                  "Time-Complexity"); the breakdown record
                                  numbers its levels on from the switch.
                                  0: one-sided throughout.  Must be 0 with
-                                 FP32_REFINE; ignored by PCR.               */
+                                 FP32_REFINE; ignored by PCR.  The Python
+                                 binding's default: 64 for m <= 32, 16 for
+                                 m <= 64, 8 above (largest m of the plan). */
 } crsolve_desc;
 
 /* One per system, in device memory, written by factor / solve. */

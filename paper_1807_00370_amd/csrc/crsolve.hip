@@ -425,7 +425,12 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
             // levels with at most one block per CU spread the panel tiles over
             // eight waves instead of four
             const unsigned nthr = L.total <= kPotrfWideBlocks ? 512 : 256;
-            if (L.cls == kBig)
+            if (L.cls == kBig && L.total <= kPotrfWideBlocks)
+                // few blocks: one block's chain of panels sets the time
+                hipLaunchKernelGGL((crs::k_potrf_rl<T, EI, RE>), dim3((unsigned)L.total), dim3(512), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, (const EI*)inA,
+                                   (cx<T>*)c.ws, c.flags);
+            else if (L.cls == kBig)
                 hipLaunchKernelGGL((crs::k_potrf_big<T, false, EI, RE>), dim3((unsigned)L.total), dim3(nthr), 0,
                                    c.st, c.dsegs + L.seg0, L.nseg, L.total, (const EI*)inA,
                                    (cx<T>*)c.ws, c.flags);
@@ -439,10 +444,24 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
             constexpr int NC = crs::trsm_strips<T>();
             const int ngrp = (ns + NC - 1) / NC;
             Timed tm(c.p, KID_TRSM, c.st, L.cls, L.f64);
-            if (sizeof(T) == 8 && L.total >= kTrsmStripBlocks)
-                hipLaunchKernelGGL((crs::k_trsm_strip<T, EI, RE>), dim3(grid8(L.total * ns)), dim3(64), 0,
+            if (sizeof(T) == 8 && L.total >= kTrsmStripBlocks && L.cls == kBig)
+                hipLaunchKernelGGL((crs::k_trsm_strip<T, EI, RE, 1>), dim3(grid8(L.total * ns)), dim3(64), 0,
                                    c.st, c.dsegs + L.seg0, L.nseg, L.total, ns, mat, rhs,
                                    (const EI*)inB, (const EI*)iny, (cx<T>*)c.ws, c.flags);
+            else if (sizeof(T) == 8 && L.cls == kBig)
+                // few blocks: every strip's chain of loads in flight eight
+                // contraction steps deep
+                hipLaunchKernelGGL((crs::k_trsm_strip<T, EI, RE, 1, 8>), dim3(grid8(L.total * ns)), dim3(64), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, ns, mat, rhs,
+                                   (const EI*)inB, (const EI*)iny, (cx<T>*)c.ws, c.flags);
+            else if (sizeof(T) == 8 && L.total >= kTrsmStripBlocks) {
+                // blocks of 33..64: two strips per wave, ceil(S / 2) items per
+                // B and ceil(K16 / 2) of y
+                const int ni = (mat ? 2 * ((b.S + 1) / 2) : 0) + (rhs ? (b.K16 + 1) / 2 : 0);
+                hipLaunchKernelGGL((crs::k_trsm_strip<T, EI, RE, 2>), dim3(grid8(L.total * ni)), dim3(64), 0,
+                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, ni, mat, rhs,
+                                   (const EI*)inB, (const EI*)iny, (cx<T>*)c.ws, c.flags);
+            }
             else
                 hipLaunchKernelGGL((crs::k_trsm_big<T, EI, RE>), dim3(grid8(L.total * ngrp)), dim3(64 * b.S),
                                    0, c.st, c.dsegs + L.seg0, L.nseg, L.total, ngrp, mat, rhs,

@@ -291,6 +291,89 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The diagonal step of panel I of the tiled Cholesky, run by one wave: the
+// tile S_II (lower triangle in sT, leading dimension 17) is factored by the
+// left-looking lane-per-row Cholesky, lane r & 15 keeping row r in registers
+// and the later columns reading the finished rows by broadcast (scalar
+// registers for RB, else LDS over sT); then lane r forms column r of
+// D_I = L_II^{-1} by forward substitution.  L_II goes to L (diagonal
+// {L_cc, 1 / L_cc}), D_I to Dg and to sD (leading dimension 17).  Returns
+// true on a pivot that is not > 0.
+template <class T, bool RB>
+__device__ __forceinline__ bool potrf_diag_tile(cx<T>* sT, cx<T>* sD, cx<T>* __restrict__ Lg,
+                                                cx<T>* __restrict__ Dg, int m, int I)
+{
+    const int lane = threadIdx.x & 63, c0 = 16 * I;
+    const int r = lane & 15, gi = c0 + r;
+    const bool real = gi < m;
+    cx<T> a[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        if (real)
+            a[u] = u <= r ? sT[r * 17 + u] : czero<T>();
+        else
+            a[u] = u == r ? cx<T>{T(1), T(0)} : czero<T>();
+        if (u == r)
+            a[u].i = T(0);
+    }
+    bool fail = false;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        cx<T> s0 = a[c], s1 = czero<T>();
+#pragma unroll
+        for (int u = 0; u + 1 < c; u += 2) {
+            if constexpr (RB) {
+                msub_cb(s0, a[u], lane_bcast(a[u], c));
+                msub_cb(s1, a[u + 1], lane_bcast(a[u + 1], c));
+            } else {
+                msub_cb(s0, a[u], sT[c * 17 + u]);
+                msub_cb(s1, a[u + 1], sT[c * 17 + u + 1]);
+            }
+        }
+        if (c & 1)
+            msub_cb(s0, a[c - 1], RB ? lane_bcast(a[c - 1], c) : sT[c * 17 + c - 1]);
+        const cx<T> sv{s0.r + s1.r, s0.i + s1.i};
+        const T dg = RB ? lane_bcast(sv.r, c) : __shfl(sv.r, c);
+        const T inv = rsqrt_nr(dg);
+        const T sq = dg * inv;
+        fail |= (c0 + c < m) && !(dg > T(0));
+        if (r == c)
+            a[c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
+        else if (r > c)
+            a[c] = cx<T>{sv.r * inv, sv.i * inv};
+        if constexpr (!RB) {
+            if (lane < 16)
+                sT[r * 17 + c] = a[c];
+            wave_lds_sync();
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (lane < 16 && real) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (u <= r)
+                Lg[(int64_t)gi * m + c0 + u] = a[u];
+    }
+    cx<T> z[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        cx<T> v = q == r ? cx<T>{T(1), T(0)} : czero<T>();
+#pragma unroll
+        for (int u = 0; u < q; ++u)
+            msub(v, RB ? lane_bcast(a[u], q) : sT[q * 17 + u], z[u]);
+        const T iq = RB ? lane_bcast(a[q].i, q) : sT[q * 17 + q].i;
+        z[q] = cx<T>{v.r * iq, v.i * iq};
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            Dg[I * 256 + q * 16 + r] = z[q];
+            sD[q * 17 + r] = z[q];
+        }
+    }
+    return fail;
+}
+
 // ------------------------------------------------------------- k_potrf_big
 
 // RB: the diagonal tile's Cholesky and inverse read the rows of L through
@@ -354,73 +437,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2,
         // registers); then lane r forms column r of D = L_II^{-1} by forward
         // substitution
         if (wv == 0) {
-            const int r = lane & 15, gi = c0 + r;
-            const bool real = gi < m;
-            cx<T> a[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                if (real)
-                    a[u] = u <= r ? sT[r * 17 + u] : czero<T>();
-                else
-                    a[u] = u == r ? cx<T>{T(1), T(0)} : czero<T>();
-                if (u == r)
-                    a[u].i = T(0);
-            }
-            bool fail = false;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                cx<T> s0 = a[c], s1 = czero<T>();
-#pragma unroll
-                for (int u = 0; u + 1 < c; u += 2) {
-                    if constexpr (RB) {
-                        msub_cb(s0, a[u], lane_bcast(a[u], c));
-                        msub_cb(s1, a[u + 1], lane_bcast(a[u + 1], c));
-                    } else {
-                        msub_cb(s0, a[u], sT[c * 17 + u]);
-                        msub_cb(s1, a[u + 1], sT[c * 17 + u + 1]);
-                    }
-                }
-                if (c & 1)
-                    msub_cb(s0, a[c - 1], RB ? lane_bcast(a[c - 1], c) : sT[c * 17 + c - 1]);
-                const cx<T> sv{s0.r + s1.r, s0.i + s1.i};
-                const T dg = RB ? lane_bcast(sv.r, c) : __shfl(sv.r, c);
-                const T inv = rsqrt_nr(dg);
-                const T sq = dg * inv;
-                fail |= (c0 + c < m) && !(dg > T(0));
-                if (r == c)
-                    a[c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
-                else if (r > c)
-                    a[c] = cx<T>{sv.r * inv, sv.i * inv};
-                if constexpr (!RB) {
-                    if (lane < 16)
-                        sT[r * 17 + c] = a[c];
-                    wave_lds_sync();
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if (lane < 16 && real) {
-#pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    if (u <= r)
-                        Lg[(int64_t)gi * m + c0 + u] = a[u];
-            }
-            cx<T> z[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                cx<T> v = q == r ? cx<T>{T(1), T(0)} : czero<T>();
-#pragma unroll
-                for (int u = 0; u < q; ++u)
-                    msub(v, RB ? lane_bcast(a[u], q) : sT[q * 17 + u], z[u]);
-                const T iq = RB ? lane_bcast(a[q].i, q) : sT[q * 17 + q].i;
-                z[q] = cx<T>{v.r * iq, v.i * iq};
-            }
-            if (lane < 16) {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    Dg[I * 256 + q * 16 + r] = z[q];
-                    sD[q * 17 + r] = z[q];
-                }
-            }
+            const bool fail = potrf_diag_tile<T, RB>(sT, sD, Lg, Dg, m, I);
             if (lane == 0 && fail)
                 sFail = 1;
         }
@@ -438,6 +455,150 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2,
                 if (i < m && j < m)
                     Lg[(int64_t)i * m + j] = cx<T>{acc.re(0, 0, v), acc.im(0, 0, v)};
             }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && sFail)
+        atomicMin(&flags[s.sys], fail_key(s.level, s.ob0 + s.obs * p));
+}
+
+// -------------------------------------------------------------- k_potrf_rl
+
+// Right-looking form of the tiled Cholesky for launches of few blocks
+// (m > 64, one work-group of eight waves per block), where one block's chain
+// of panels sets the time: k_potrf_big's left-looking panel updates wait on
+// a trip to L2 for every group of contraction steps, here each trailing tile
+// costs one load that is in flight while the previous tile is updated.  Per
+// 16-column panel I: one wave factors the diagonal tile and forms D_I
+// (potrf_diag_tile); the waves form the tiles below, L_RI = S_RI D_I^H,
+// store them to L and keep them in LDS; then every trailing tile
+// S_RC -= L_RI L_CI^H (I < C <= R) is updated in place in the L slot, both
+// operands read from LDS.  Panel 0 reads the tiles of A (Hermitian reading:
+// lower triangle, the diagonal's imaginary parts dropped when a diagonal
+// tile is factored) and writes every lower tile of the slot once; later
+// panels read and update the slot.  The trailing sums round once per panel
+// instead of once per tile: the same factorization up to rounding order.
+template <class T, class EI = cx<T>, bool RE = false>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_potrf_rl(const Seg* __restrict__ segs, int nseg,
+                                                  int64_t total, const EI* __restrict__ inA,
+                                                  cx<T>* __restrict__ W,
+                                                  unsigned long long* __restrict__ flags)
+{
+    constexpr int kMaxS = 16; // m <= 256
+    __shared__ cx<T> sT[16 * 17]; // diagonal tile S_I (row-major, leading dimension 17)
+    __shared__ cx<T> sD[16 * 17]; // D_I (leading dimension 17)
+    __shared__ cx<T> sP[(kMaxS - 1) * 256]; // L_RI of R > I: tile R - I - 1, 16 x 16 row-major
+    __shared__ int sFail;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, kr = lane >> 4, cc = lane & 15;
+    const int nw = blockDim.x >> 6;
+    const int64_t w = blockIdx.x;
+    if (w >= total)
+        return;
+    const Seg& s = segs[find_seg(segs, nseg, w)];
+    const int64_t t = w - s.w0;
+    const int p = s.e0 + (int)t * s.es;
+    const int m = s.m, S = (m + 15) >> 4;
+    if ((flags[s.sys] >> 40) < (unsigned long long)s.level)
+        return; // broke down at an earlier level
+    const int64_t mm = (int64_t)m * m;
+    const EI* Ap = inA + s.oA + (int64_t)p * mm;
+    cx<T>* Lg = W + s.oL + t * mm;
+    cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
+    if (tid == 0)
+        sFail = 0;
+    // element (i, j) of the lower triangle as panel I finds it
+    auto cur_el = [&](int I, int i, int j) -> cx<T> {
+        return I == 0 ? cvt<T>(Ap[(int64_t)i * m + j]) : Lg[(int64_t)i * m + j];
+    };
+    for (int I = 0; I < S; ++I) {
+        const int c0 = 16 * I, kd = min(16, m - c0);
+        if (wv == 0) {
+            // the diagonal tile as the trailing updates left it
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = kr * 4 + v, gi = c0 + i, gj = c0 + cc;
+                if (cc <= i && gi < m)
+                    sT[i * 17 + cc] = cur_el(I, gi, gj);
+            }
+            wave_lds_sync();
+            const bool fail = potrf_diag_tile<T, false>(sT, sD, Lg, Dg, m, I);
+            if (lane == 0 && fail)
+                sFail = 1;
+        }
+        __syncthreads();
+        // tiles below the diagonal: L_RI = S_RI D_I^H, to L and to LDS
+        for (int R = I + 1 + wv; R < S; R += nw) {
+            // contraction step q: lane (kr, cc) supplies S_RI[cc][4 q + kr]
+            // and conj(D_I[cc][4 q + kr])
+            cx<T> sa[4], db[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * R + cc, tc = 4 * q + kr;
+                sa[q] = (i < m && tc < kd) ? cur_el(I, i, c0 + tc) : czero<T>();
+                db[q] = tc < kd ? sD[cc * 17 + tc] : czero<T>();
+            }
+            Acc3<T, 1, 1, RE> acc;
+            acc.zero();
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc.step(0, 0, sa[q].r, sa[q].i, db[q].r, -db[q].i);
+            cx<T>* tp = sP + (R - I - 1) * 256;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ii = MF<T>::row(kr, v), i = 16 * R + ii, j = c0 + cc;
+                const cx<T> l{acc.re(0, 0, v), acc.im(0, 0, v)};
+                const bool in = i < m && j < m;
+                if (in)
+                    Lg[(int64_t)i * m + j] = l;
+                tp[ii * 16 + cc] = in ? l : czero<T>();
+            }
+        }
+        __syncthreads();
+        // trailing tiles (R, C), I < C <= R < S, numbered row by row; each
+        // wave loads its next tile while it updates the current one
+        const int nt = S - I - 1, ntile = nt * (nt + 1) / 2;
+        auto tile_rc = [&](int e, int& R, int& C) {
+            int r = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+            while (r * (r + 1) / 2 > e)
+                --r;
+            while ((r + 1) * (r + 2) / 2 <= e)
+                ++r;
+            R = I + 1 + r;
+            C = I + 1 + (e - r * (r + 1) / 2);
+        };
+        auto load_tile = [&](int e, cx<T>(&o)[4]) {
+            int R, C;
+            tile_rc(e, R, C);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * R + MF<T>::row(kr, v), j = 16 * C + cc;
+                o[v] = (i < m && j <= i) ? cur_el(I, i, j) : czero<T>();
+            }
+        };
+        int e = wv;
+        cx<T> cur[4];
+        if (e < ntile)
+            load_tile(e, cur);
+        for (; e < ntile; e += nw) {
+            cx<T> nxt[4] = {czero<T>(), czero<T>(), czero<T>(), czero<T>()};
+            if (e + nw < ntile)
+                load_tile(e + nw, nxt);
+            int R, C;
+            tile_rc(e, R, C);
+            Acc3<T, 1, 1, RE> acc;
+            acc.zero();
+            // operands from LDS: two contraction steps per load group suffice
+            wave_mm3<T, 1, 1, false, true, 2, RE>(acc, WOp<T>{sP + (R - I - 1) * 256, 16, 1, 16},
+                                                  WOp<T>{sP + (C - I - 1) * 256, 16, 1, 16}, kd);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * R + MF<T>::row(kr, v), j = 16 * C + cc;
+                if (i < m && j <= i)
+                    Lg[(int64_t)i * m + j] = cx<T>{cur[v].r - acc.re(0, 0, v), cur[v].i - acc.im(0, 0, v)};
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                cur[v] = nxt[v];
         }
         __syncthreads();
     }
@@ -622,12 +783,17 @@ __global__ __launch_bounds__(1024) void k_trsm_big(const Seg* __restrict__ segs,
     }
 }
 
-// One wave per (eliminated block, 16-column strip): the same substitution
-// with each wave sweeping all row tiles of its strip (no barriers).  Strips of
-// a block: with_mat gives 2 S strips (columns of B_p^H, then of B_{p-d}),
-// with_rhs ceil(k / 16) strips of y_p after them.  Used for FP64 levels with
-// many blocks, where the work-group form's idle waves would cost throughput.
-template <class T, class EI = cx<T>, bool RE = false>
+// One wave per (eliminated block, NW adjacent 16-column strips): the same
+// substitution with each wave sweeping all row tiles of its strips (no
+// barriers).  Work items of a block: with_mat gives ceil(S / NW) items of
+// columns of B_p^H, then as many of B_{p-d}, with_rhs ceil(ceil(k / 16) / NW)
+// items of y_p after them.  With NW = 2 every L tile a wave loads serves two
+// strips, which halves the L traffic through L2 and the item count (blocks of
+// 33..64; at m = 256 it measured no faster in complex and slower in real
+// form).  Used for FP64 levels with many blocks, where the work-group form's
+// idle waves would cost throughput, and with eight contraction steps per load
+// group for FP64 levels of few blocks above 64.
+template <class T, class EI = cx<T>, bool RE = false, int NW = 1, int GD = 0>
 __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs, int nseg,
                                                  int64_t total, int nstrip, int with_mat,
                                                  int with_rhs, const EI* __restrict__ inB,
@@ -649,24 +815,25 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
     if ((flags[s.sys] >> 40) < (unsigned long long)s.level)
         return;
     const int64_t mm = (int64_t)m * m, mk = (int64_t)m * k;
+    const int SI = (S + NW - 1) / NW; // items of B_p^H (and of B_{p-d})
     int src = 2;
     if (with_mat) {
-        if (u < 2 * S)
-            src = u < S ? 0 : 1;
+        if (u < 2 * SI)
+            src = u < SI ? 0 : 1;
         else
-            u -= 2 * S;
+            u -= 2 * SI;
     }
     int c0;
     if (src == 2) {
-        c0 = 16 * u;
+        c0 = 16 * NW * u;
         if (!with_rhs || c0 >= k)
             return;
     } else {
-        c0 = 16 * (src == 0 ? u : u - S);
+        c0 = 16 * NW * (src == 0 ? u : u - SI);
         if (src == 0 ? p + d >= s.n : p - d < 0)
             return;
     }
-    const int nc = min(16, (src == 2 ? k : m) - c0);
+    const int nc = min(16 * NW, (src == 2 ? k : m) - c0);
     // element (r, c) of the right-hand side is G[r * gr + c * gc]
     const EI* G;
     int gr, gc;
@@ -690,33 +857,46 @@ __global__ __launch_bounds__(64) void k_trsm_strip(const Seg* __restrict__ segs,
     const int ldo = src == 2 ? k : m;
     const cx<T>* Lg = W + s.oL + t * mm;
     const cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
+    // two complex strips keep two contraction steps per load group in flight
+    // instead of four (the same operand registers); the real form has the
+    // registers for four.  GD > 0 sets the depth (launches of few blocks,
+    // where each wave's chain of loads, not the occupancy, sets the time).
+    constexpr int GK = GD > 0 ? GD : ((NW == 1 || RE) ? 4 : 2);
     for (int I = 0; I < S; ++I) {
         const int r0 = 16 * I;
-        Acc3<T, 1, 1, RE> acc;
+        Acc3<T, 1, NW, RE> acc;
         acc.zero();
-        wave_mm3<T, 1, 1, false, false, 4, RE>(acc, WOp<T>{Lg + (int64_t)r0 * m, m, 1, m - r0},
-                                               WOp<T>{out + c0, 1, ldo, nc}, r0);
+        wave_mm3<T, 1, NW, false, false, GK, RE>(acc, WOp<T>{Lg + (int64_t)r0 * m, m, 1, m - r0},
+                                                WOp<T>{out + c0, 1, ldo, nc}, r0);
         // w = G_I - acc stays in the accumulator layout: register v of lane
         // (kr, cc) holds row MF::row(kr, v) of column cc, which is the right
         // operand of contraction step v once the left operand D_I supplies
         // column MF::row(kr, v) of its row cc
-        Acc3<T, 1, 1, RE> x;
+        Acc3<T, 1, NW, RE> x;
         x.zero();
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int rr = MF<T>::row(kr, v), r = r0 + rr;
-            cx<T> g = (r < m && cc < nc) ? cvt<T>(G[r * gr + (c0 + cc) * gc]) : czero<T>();
-            if (src == 0)
-                g.i = -g.i;
-            const T br = g.r - acc.re(0, 0, v), bi = g.i - acc.im(0, 0, v);
             const cx<T> a = Dg[I * 256 + cc * 16 + rr];
-            x.step(0, 0, a.r, a.i, br, bi);
+#pragma unroll
+            for (int b = 0; b < NW; ++b) {
+                const int c = 16 * b + cc;
+                cx<T> g = (r < m && c < nc) ? cvt<T>(G[r * gr + (c0 + c) * gc]) : czero<T>();
+                if (src == 0)
+                    g.i = -g.i;
+                const T br = g.r - acc.re(0, b, v), bi = g.i - acc.im(0, b, v);
+                x.step(0, b, a.r, a.i, br, bi);
+            }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = r0 + MF<T>::row(kr, v);
-            if (r < m && cc < nc)
-                out[(int64_t)r * ldo + c0 + cc] = cx<T>{x.re(0, 0, v), x.im(0, 0, v)};
+#pragma unroll
+            for (int b = 0; b < NW; ++b) {
+                const int c = 16 * b + cc;
+                if (r < m && c < nc)
+                    out[(int64_t)r * ldo + c0 + c] = cx<T>{x.re(0, b, v), x.im(0, b, v)};
+            }
         }
         __syncthreads(); // the rows just stored are the next tiles' operands
     }

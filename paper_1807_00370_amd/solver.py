@@ -18,6 +18,17 @@ from . import _lib
 _DT = {torch.complex128: _lib.C128, torch.complex64: _lib.C64, torch.float64: _lib.R64,
        torch.float32: _lib.R32}
 PCR_TAIL_DEFAULT = 64
+
+
+def pcr_tail_default(ms) -> int:
+    """Block count at which the default schedule switches from one-sided
+    levels to Algorithm 1, by the largest block size of the plan: 64 for
+    m <= 32, 16 for m <= 64, 8 above (the fastest switch points measured at
+    N = 65536, m = 32, k = 16; N = 16384, m = 64, k = 32; N = 4096, m = 256,
+    k = 1: the larger the blocks, the dearer a level of Algorithm 1, which
+    keeps every block of its system)."""
+    mx = max(int(m) for m in ms)
+    return PCR_TAIL_DEFAULT if mx <= 32 else (16 if mx <= 64 else 8)
 _PREC = {"native": _lib.PREC_NATIVE, "fp32_refine": _lib.PREC_FP32_REFINE}
 _SCHED = {"cr": _lib.SCHED_CR, "pcr": _lib.SCHED_PCR}
 
@@ -61,10 +72,10 @@ class Solver:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.dtype = dtype
         if pcr_tail_blocks is None:
-            # one-sided levels down to 64 blocks, then Algorithm 1 (fastest
-            # switch point measured at N = 65536, m = 32, k = 16); the mixed
-            # form stays one-sided
-            pcr_tail_blocks = PCR_TAIL_DEFAULT if (precision == "native" and schedule == "cr") else 0
+            # one-sided levels down to pcr_tail_default(ms) blocks, then
+            # Algorithm 1; the mixed form stays one-sided
+            pcr_tail_blocks = (pcr_tail_default(ms) if (precision == "native" and schedule == "cr")
+                               else 0)
         self.pcr_tail_blocks = pcr_tail_blocks
         self.plan = _lib.Plan(Ns, ms, ks, _DT[dtype], _PREC[precision], _SCHED[schedule], rtol,
                               max_refine, fp64_tail_blocks, pcr_tail_blocks)

@@ -46,9 +46,10 @@ def test_check_hpd_matches_eigenvalues(tdev, N, m, sign):
     At, Bt = (torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (A, s.B))
     ok, rec = check_hpd(At, Bt)
     assert ok == (sign > 0)
-    # the default schedule: one-sided levels, then Algorithm 1 from 64 blocks
-    from paper_1807_00370_amd.solver import PCR_TAIL_DEFAULT
-    _, io = oracle.solve_hybrid(A, s.B, s.y, PCR_TAIL_DEFAULT)
+    # the default schedule: one-sided levels, then Algorithm 1 from the
+    # block-size dependent switch point
+    from paper_1807_00370_amd.solver import pcr_tail_default
+    _, io = oracle.solve_hybrid(A, s.B, s.y, pcr_tail_default([m]))
     assert (int(rec["status"]), int(rec["level"]), int(rec["block"])) == \
         (io["status"], io["level"], io["block"])
 

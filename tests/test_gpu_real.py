@@ -36,14 +36,14 @@ CASES = [(1000, 4, 1), (777, 16, 4), (513, 32, 16), (300, 64, 8), (200, 80, 2), 
 @pytest.mark.parametrize("N,m,k", CASES)
 def test_real_matches_oracle_and_complex_path(tdev, N, m, k):
     torch, dev = tdev
-    from paper_1807_00370_amd.solver import Solver, PCR_TAIL_DEFAULT
+    from paper_1807_00370_amd.solver import Solver, pcr_tail_default
     print("case real N=%d m=%d k=%d" % (N, m, k), flush=True)
     s = W.random_spd(N, m, k, 9300 + N + m + k)
     A, B, y = (torch.from_numpy(v).to(dev) for v in (s.A, s.B, s.y))
     sol = Solver([N], [m], [k], dtype=torch.float64, device=dev)
     x = sol.factor_solve(A, B, y).cpu().numpy()
     assert x.dtype == np.float64
-    xo, io = oracle.solve_hybrid(s.A, s.B, s.y, PCR_TAIL_DEFAULT)
+    xo, io = oracle.solve_hybrid(s.A, s.B, s.y, pcr_tail_default([m]))
     assert _rec(sol.info_host()[0]) == io
     assert np.all(xo.imag == 0.0)
     assert _rel(x, xo.real) <= 1e-11
@@ -63,7 +63,7 @@ def test_real_matches_oracle_and_complex_path(tdev, N, m, k):
 
 def test_real_factor_then_solve_and_breakdown(tdev):
     torch, dev = tdev
-    from paper_1807_00370_amd.solver import Solver, solve, PCR_TAIL_DEFAULT
+    from paper_1807_00370_amd.solver import Solver, solve, pcr_tail_default
     s = W.random_spd(600, 40, 3, 77)
     A, B, y = (torch.from_numpy(v).to(dev) for v in (s.A, s.B, s.y))
     sol = Solver([600], [40], [3], dtype=torch.float64, device=dev)
@@ -74,7 +74,7 @@ def test_real_factor_then_solve_and_breakdown(tdev):
     assert _rel(x2, xo2.real) <= 1e-11
     t = W.random_spd(300, 12, 2, 78, shift_scale=2.0)
     x, rec = solve(*(torch.from_numpy(v).to(dev) for v in (t.A, t.B, t.y)))
-    _, io = oracle.solve_hybrid(t.A, t.B, t.y, PCR_TAIL_DEFAULT)
+    _, io = oracle.solve_hybrid(t.A, t.B, t.y, pcr_tail_default([12]))
     assert _rec(rec) == io == dict(status=1, level=0, block=1)
     assert np.isnan(x.cpu().numpy()).all()
 
