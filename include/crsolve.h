@@ -131,8 +131,8 @@ typedef struct {
                                  numbers its levels on from the switch.
                                  0: one-sided throughout.  Must be 0 with
                                  FP32_REFINE; ignored by PCR.  The Python
-                                 binding's default: 64 for m <= 32, 16 for
-                                 m <= 64, 8 above (largest m of the plan). */
+                                 binding's default by the plan's largest
+                                 block: 64 up to 32, 16 up to 64, 8 above. */
 } crsolve_desc;
 
 /* One per system, in device memory, written by factor / solve. */
