@@ -131,12 +131,28 @@ __device__ __forceinline__ void put_x(cx<T>* xp, cx<double>* up, int upd, int64_
 // q = p + d (solved at the deeper levels) into the FP64 solution: elements
 // [e0, e1) with stride es of u_q (+)= d_q.  Every kept block of level 0 has
 // exactly one eliminated left neighbour, so each is updated once.
+// Four elements at a time: their loads are issued together (element e0
+// stands in past the end), so a chunk costs one round trip rather than one
+// per element waiting behind the previous store.
 template <class T>
 __device__ __forceinline__ void put_kept(const cx<T>* dq, cx<double>* uq, int upd, int64_t e0,
                                          int64_t e1, int64_t es)
 {
-    for (int64_t e = e0; e < e1; e += es)
-        put_x<T>(nullptr, uq, upd, e, dq[e]);
+    constexpr int U = 4;
+    for (int64_t e = e0; e < e1; e += U * es) {
+        cx<T> dv[U];
+        cx<double> ov[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t ei = e + u * es < e1 ? e + u * es : e0;
+            dv[u] = dq[ei];
+            ov[u] = upd == 2 ? uq[ei] : cx<double>{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e + u * es < e1)
+                uq[e + u * es] = cx<double>{ov[u].r + (double)dv[u].r, ov[u].i + (double)dv[u].i};
+    }
 }
 
 constexpr unsigned long long kNoFail = ~0ull;

@@ -442,13 +442,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2,
                 sFail = 1;
         }
         __syncthreads();
-        // tiles below the diagonal: L[R][I] = S_R D_I^H, in place
+        // tiles below the diagonal: L[R][I] = S_R D_I^H, in place.  Step q of
+        // the contraction: lane (kr, cc) supplies S_R[cc][4 q + kr] and
+        // conj(D_I[cc][4 q + kr]), the latter read from the LDS array itself
+        // (a generic pointer would give flat loads, which wait behind the
+        // wave's global stores of its previous tile)
         for (int R = I + 1 + wv; R < S; R += nw) {
+            const int kd = min(16, m - c0);
+            cx<T> sa[4], db[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * R + cc, tc = 4 * q + kr;
+                sa[q] = (i < m && tc < kd) ? Lg[(int64_t)i * m + c0 + tc] : czero<T>();
+                db[q] = tc < kd ? sD[cc * 17 + tc] : czero<T>();
+            }
             Acc3<T, 1, 1, RE> acc;
             acc.zero();
-            wave_mm3<T, 1, 1, false, true, 4, RE>(acc,
-                                              WOp<T>{Lg + (int64_t)16 * R * m + c0, m, 1, m - 16 * R},
-                                              WOp<T>{sD, 17, 1, 16}, min(16, m - c0));
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc.step(0, 0, sa[q].r, sa[q].i, db[q].r, -db[q].i);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * R + MF<T>::row(kr, v), j = c0 + cc;
@@ -967,6 +979,29 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
     const cx<T>* Qr = W + s.oQ + tr * mm;
     const cx<T>* Pr = W + s.oP + tr * mm;
     const int i0 = TT * ti, j0 = TT * tj;
+    // 16 x 16 tiles: the elements of A_q (kind 0) or y_q (kind 2) this lane
+    // subtracts from, loaded first and in every lane (element 0 stands in):
+    // the loads overlap the products and none waits behind a store of the
+    // tile (32 x 32 tiles, short of registers, load each before its store)
+    cx<T> xo[TW][TW][4];
+    auto load_xo = [&] {
+        if (kind == 1)
+            return;
+        const EI* src = kind == 0 ? inA + s.oA + q * mm : iny + s.oy + q * mk;
+        const int ld = kind == 0 ? m : k;
+#pragma unroll
+        for (int a = 0; a < TW; ++a)
+#pragma unroll
+            for (int b = 0; b < TW; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + 16 * a + MF<T>::row(kr, v), j = j0 + 16 * b + cc;
+                    const bool ok = i < m && (kind == 0 ? j <= i : j < k);
+                    xo[a][b][v] = cvt<T>(src[ok ? i * ld + j : 0]);
+                }
+    };
+    if constexpr (TW == 1)
+        load_xo();
     Acc3<T, TW, TW, RE> acc;
     acc.zero();
     if (kind == 0) {
@@ -976,7 +1011,6 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
         if (hasR)
             wave_mm3<T, TW, TW, true, false, 2 / TW, RE>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{Qr + j0, 1, m, m - j0}, m);
-        const EI* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll
         for (int a = 0; a < TW; ++a)
@@ -986,7 +1020,7 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                 for (int v = 0; v < 4; ++v) {
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), j = j0 + 16 * b + cc;
                     if (i < m && j <= i) {
-                        const cx<T> x = cvt<T>(Aq[i * m + j]);
+                        const cx<T> x = TW == 1 ? xo[a][b][v] : cvt<T>(inA[s.oA + q * mm + i * m + j]);
                         cx<T> o{x.r - acc.re(a, b, v), x.i - acc.im(a, b, v)};
                         if (i == j)
                             o.i = T(0);
@@ -1016,7 +1050,6 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
         if (hasR)
             wave_mm3<T, TW, TW, true, false, 2 / TW, RE>(acc, WOp<T>{Qr + i0, 1, m, m - i0},
                                              WOp<T>{gr + j0, 1, k, k - j0}, m);
-        const EI* yq = iny + s.oy + q * mk;
         cx<T>* vo = W + s.oyo + oi * mk;
 #pragma unroll
         for (int a = 0; a < TW; ++a)
@@ -1026,7 +1059,7 @@ __global__ __launch_bounds__(64) void k_reduce_big(const Seg* __restrict__ segs,
                 for (int v = 0; v < 4; ++v) {
                     const int i = i0 + 16 * a + MF<T>::row(kr, v), c = j0 + 16 * b + cc;
                     if (i < m && c < k) {
-                        const cx<T> x = cvt<T>(yq[i * k + c]);
+                        const cx<T> x = TW == 1 ? xo[a][b][v] : cvt<T>(iny[s.oy + q * mk + i * k + c]);
                         vo[i * k + c] = cx<T>{x.r - acc.re(a, b, v), x.i - acc.im(a, b, v)};
                     }
                 }
@@ -1266,12 +1299,27 @@ __global__ __launch_bounds__(1024) void k_back_big(const Seg* __restrict__ segs,
     const cx<T>* xm = X + s.ox + (s.xo + s.xs * (p - d)) * mk;
     const cx<T>* xn = X + s.ox + (s.xo + s.xs * (p + d)) * mk;
     if (upd && hasNext) {
-        // this strip's columns of the kept neighbour's correction
-        for (int e = threadIdx.x; e < m * 16; e += blockDim.x)
-            if ((e & 15) < nc) {
-                const int64_t o = (e >> 4) * k + c0 + (e & 15);
-                put_x<T>(nullptr, up + d * mk, upd, o, xn[o]);
-            }
+        // this strip's columns of the kept neighbour's correction (at most
+        // four elements per thread: blockDim = 64 ceil(m / 16)), their loads
+        // issued together before the stores
+        cx<double>* uq = up + d * mk;
+        cx<T> dv[4];
+        cx<double> ov[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = threadIdx.x + u * blockDim.x;
+            const bool ok = e < m * 16 && (e & 15) < nc;
+            const int64_t o = ok ? (e >> 4) * k + c0 + (e & 15) : 0;
+            dv[u] = xn[o];
+            ov[u] = upd == 2 ? uq[o] : cx<double>{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = threadIdx.x + u * blockDim.x;
+            if (e < m * 16 && (e & 15) < nc)
+                uq[(e >> 4) * k + c0 + (e & 15)] =
+                    cx<double>{ov[u].r + (double)dv[u].r, ov[u].i + (double)dv[u].i};
+        }
     }
     const cx<T>* L = W + s.oL + t * mm;
     const cx<T>* P = W + s.oP + t * mm;

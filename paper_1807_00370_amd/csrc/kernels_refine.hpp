@@ -244,13 +244,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 prev();
             else
                 next();
+            // y's elements loaded together, in every lane (element 0 stands
+            // in), before the first store of r: one round trip, not one per
+            // element behind the previous store
+            cx<T> yv[RM][4];
+#pragma unroll
+            for (int a = 0; a < RM; ++a)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = r0 + 16 * a + MF<T>::row(kr, u), c = c0 + cc;
+                    yv[a][u] = yj[(i < m && c < k) ? i * k + c : 0];
+                }
 #pragma unroll
             for (int a = 0; a < RM; ++a)
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int i = r0 + 16 * a + MF<T>::row(kr, u), c = c0 + cc;
                     if (i < m && c < k) {
-                        const cx<T> y = yj[i * k + c];
+                        const cx<T> y = yv[a][u];
                         const cx<T> r{y.r - cr[a][0][u], y.i - ci[a][0][u]};
                         sr += r.r * r.r + r.i * r.i;
                         sy += y.r * y.r + y.i * y.i;
