@@ -861,38 +861,52 @@ __global__ __launch_bounds__(64, 2) void k_reduce_m(const Seg* __restrict__ segs
                 mma_hn3<T, MT / 4>(ay[i], X[i], G);
         }
     }
+    // the epilogues load the four A_q or y_q elements of a tile together, in
+    // every lane (element 0 stands in), before their stores: one round trip
+    // per tile instead of one per element waiting behind the previous store
     if (with_mat) {
         const EI* Aq = inA + s.oA + q * mm;
         cx<T>* Vo = W + s.oAo + oi * mm;
 #pragma unroll
         for (int i = 0, v = 0; i < NT16; ++i)
 #pragma unroll
-            for (int j = 0; j <= i; ++j, ++v)
+            for (int j = 0; j <= i; ++j, ++v) {
+                cx<T> xa[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int a = 16 * i + MF<T>::row(kr, u), b = 16 * j + cc;
+                    xa[u] = cvt<T>(Aq[(a < m && b <= a) ? a * m + b : 0]);
+                }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int a = 16 * i + MF<T>::row(kr, u), b = 16 * j + cc;
                     if (a < m && b <= a) {
-                        const cx<T> x = cvt<T>(Aq[a * m + b]);
-                        cx<T> o{x.r - av[v].re(0, 0, u), x.i - av[v].im(0, 0, u)};
+                        cx<T> o{xa[u].r - av[v].re(0, 0, u), xa[u].i - av[v].im(0, 0, u)};
                         if (a == b)
                             o.i = T(0);
                         Vo[a * m + b] = o;
                     }
                 }
+            }
     }
     if (kc0) {
         const EI* yq = iny + s.oy + q * mk;
         cx<T>* yo = W + s.oyo + oi * mk;
 #pragma unroll
-        for (int i = 0; i < NT16; ++i)
+        for (int i = 0; i < NT16; ++i) {
+            cx<T> xy[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int a = 16 * i + MF<T>::row(kr, u), c = cc;
-                if (a < m && c < kc0) {
-                    const cx<T> x = cvt<T>(yq[a * k + c]);
-                    yo[a * k + c] = cx<T>{x.r - ay[i].re(0, 0, u), x.i - ay[i].im(0, 0, u)};
-                }
+                xy[u] = cvt<T>(yq[(a < m && c < kc0) ? a * k + c : 0]);
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int a = 16 * i + MF<T>::row(kr, u), c = cc;
+                if (a < m && c < kc0)
+                    yo[a * k + c] = cx<T>{xy[u].r - ay[i].re(0, 0, u), xy[u].i - ay[i].im(0, 0, u)};
+            }
+        }
     }
     // phase 3: B'_q = -P_r^H Q_r (Q_r tiles are still in X when hasR)
     if (with_mat && hasR && r + d < n) {
