@@ -478,18 +478,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RB ? 3 : 2,
 
 // Right-looking form of the tiled Cholesky for launches of few blocks
 // (m > 64, one work-group of eight waves per block), where one block's chain
-// of panels sets the time: k_potrf_big's left-looking panel updates wait on
-// a trip to L2 for every group of contraction steps, here each trailing tile
-// costs one load that is in flight while the previous tile is updated.  Per
-// 16-column panel I: one wave factors the diagonal tile and forms D_I
-// (potrf_diag_tile); the waves form the tiles below, L_RI = S_RI D_I^H,
-// store them to L and keep them in LDS; then every trailing tile
-// S_RC -= L_RI L_CI^H (I < C <= R) is updated in place in the L slot, both
-// operands read from LDS.  Panel 0 reads the tiles of A (Hermitian reading:
-// lower triangle, the diagonal's imaginary parts dropped when a diagonal
-// tile is factored) and writes every lower tile of the slot once; later
-// panels read and update the slot.  The trailing sums round once per panel
-// instead of once per tile: the same factorization up to rounding order.
+// of panels sets the time.  Per 16-column panel I: the waves form the tiles
+// below the diagonal, L_RI = S_RI D_I^H, into L and into LDS; then wave 0
+// runs ahead on the next panel -- S_JJ -= L_JI L_JI^H for J = I + 1, straight
+// into LDS, and the diagonal step of panel J (potrf_diag_tile: L_JJ, D_J) --
+// while the other seven waves update the remaining trailing tiles
+// S_RC -= L_RI L_CI^H (I < C <= R) in place in the L slot, eight tiles per
+// batch of loads, both product operands from LDS.  The diagonal steps, a
+// chain of one wave, thus overlap the trailing updates instead of idling
+// the work-group.  Panel 0 reads the tiles of A (Hermitian reading: lower
+// triangle, the diagonal's imaginary parts dropped when a diagonal tile is
+// factored) and writes every lower tile of the slot once; later panels read
+// and update the slot.  The trailing sums round once per panel: the same
+// factorization as k_potrf_big up to rounding order.
 template <class T, class EI = cx<T>, bool RE = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_potrf_rl(const Seg* __restrict__ segs, int nseg,
                                                   int64_t total, const EI* __restrict__ inA,
@@ -497,6 +498,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                                                   unsigned long long* __restrict__ flags)
 {
     constexpr int kMaxS = 16; // m <= 256
+    constexpr int TB = 8;     // trailing tiles per batch of loads
     __shared__ cx<T> sT[16 * 17]; // diagonal tile S_I (row-major, leading dimension 17)
     __shared__ cx<T> sD[16 * 17]; // D_I (leading dimension 17)
     __shared__ cx<T> sP[(kMaxS - 1) * 256]; // L_RI of R > I: tile R - I - 1, 16 x 16 row-major
@@ -511,42 +513,47 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     const int p = s.e0 + (int)t * s.es;
     const int m = s.m, S = (m + 15) >> 4;
     if ((flags[s.sys] >> 40) < (unsigned long long)s.level)
-        return; // broke down at an earlier level
+        return;
     const int64_t mm = (int64_t)m * m;
     const EI* Ap = inA + s.oA + (int64_t)p * mm;
     cx<T>* Lg = W + s.oL + t * mm;
     cx<T>* Dg = W + s.oD + t * (int64_t)S * 256;
+    // element (i, j) of the lower triangle as panel I finds it, zero unless
+    // ok; the load is issued in every lane (element (0, 0) stands in), so a
+    // wave's count of memory operations in flight stays exact
+    auto cur_el = [&](int I, int i, int j, bool ok) -> cx<T> {
+        const int64_t e = ok ? (int64_t)i * m + j : 0;
+        const cx<T> v = I == 0 ? cvt<T>(Ap[e]) : Lg[e];
+        return ok ? v : czero<T>();
+    };
     if (tid == 0)
         sFail = 0;
-    // element (i, j) of the lower triangle as panel I finds it
-    auto cur_el = [&](int I, int i, int j) -> cx<T> {
-        return I == 0 ? cvt<T>(Ap[(int64_t)i * m + j]) : Lg[(int64_t)i * m + j];
-    };
+    bool fail = false;
+    // panel 0's diagonal step (later ones run ahead, during the previous
+    // panel's trailing updates)
+    if (wv == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = kr * 4 + v;
+            const cx<T> e = cur_el(0, i, cc, cc <= i && i < m);
+            if (cc <= i && i < m)
+                sT[i * 17 + cc] = e;
+        }
+        wave_lds_sync();
+        fail |= potrf_diag_tile<T, false>(sT, sD, Lg, Dg, m, 0);
+    }
+    __syncthreads();
     for (int I = 0; I < S; ++I) {
         const int c0 = 16 * I, kd = min(16, m - c0);
-        if (wv == 0) {
-            // the diagonal tile as the trailing updates left it
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = kr * 4 + v, gi = c0 + i, gj = c0 + cc;
-                if (cc <= i && gi < m)
-                    sT[i * 17 + cc] = cur_el(I, gi, gj);
-            }
-            wave_lds_sync();
-            const bool fail = potrf_diag_tile<T, false>(sT, sD, Lg, Dg, m, I);
-            if (lane == 0 && fail)
-                sFail = 1;
-        }
-        __syncthreads();
-        // tiles below the diagonal: L_RI = S_RI D_I^H, to L and to LDS
+        // tiles below the diagonal: L_RI = S_RI D_I^H, to L and to LDS.
+        // Contraction step q: lane (kr, cc) supplies S_RI[cc][4 q + kr] and
+        // conj(D_I[cc][4 q + kr])
         for (int R = I + 1 + wv; R < S; R += nw) {
-            // contraction step q: lane (kr, cc) supplies S_RI[cc][4 q + kr]
-            // and conj(D_I[cc][4 q + kr])
             cx<T> sa[4], db[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i = 16 * R + cc, tc = 4 * q + kr;
-                sa[q] = (i < m && tc < kd) ? cur_el(I, i, c0 + tc) : czero<T>();
+                sa[q] = cur_el(I, i, c0 + tc, i < m && tc < kd);
                 db[q] = tc < kd ? sD[cc * 17 + tc] : czero<T>();
             }
             Acc3<T, 1, 1, RE> acc;
@@ -566,54 +573,89 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             }
         }
         __syncthreads();
-        // trailing tiles (R, C), I < C <= R < S, numbered row by row; each
-        // wave loads its next tile while it updates the current one
-        const int nt = S - I - 1, ntile = nt * (nt + 1) / 2;
-        auto tile_rc = [&](int e, int& R, int& C) {
-            int r = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
-            while (r * (r + 1) / 2 > e)
-                --r;
-            while ((r + 1) * (r + 2) / 2 <= e)
-                ++r;
-            R = I + 1 + r;
-            C = I + 1 + (e - r * (r + 1) / 2);
-        };
-        auto load_tile = [&](int e, cx<T>(&o)[4]) {
-            int R, C;
-            tile_rc(e, R, C);
+        if (I + 1 < S) {
+            const int nt = S - I - 1, ntile = nt * (nt + 1) / 2;
+            if (wv == 0) {
+                // look-ahead: S_JJ -= L_JI L_JI^H for J = I + 1 (sP tile 0),
+                // straight into sT, then the diagonal step of panel J
+                const int J = I + 1, cJ = 16 * J;
+                Acc3<T, 1, 1, RE> acc;
+                acc.zero();
+                const int ta = cc * 16 + kr;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = 16 * R + MF<T>::row(kr, v), j = 16 * C + cc;
-                o[v] = (i < m && j <= i) ? cur_el(I, i, j) : czero<T>();
+                for (int q = 0; q < 4; ++q) {
+                    const cx<T> a = sP[ta + 4 * q];
+                    acc.step(0, 0, a.r, a.i, a.r, -a.i);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = MF<T>::row(kr, v), gi = cJ + i, gj = cJ + cc;
+                    const bool ok = cc <= i && gi < m;
+                    const cx<T> o = cur_el(I, gi, gj, ok);
+                    if (ok)
+                        sT[i * 17 + cc] = cx<T>{o.r - acc.re(0, 0, v), o.i - acc.im(0, 0, v)};
+                }
+                wave_lds_sync();
+                fail |= potrf_diag_tile<T, false>(sT, sD, Lg, Dg, m, J);
+            } else {
+                // the other trailing tiles S_RC -= L_RI L_CI^H, I < C <= R, row
+                // by row (tile 0 is the look-ahead's), TB at a time: their
+                // loads issued together before the stores, in every lane
+                auto tile_rc = [&](int e, int& R, int& C) {
+                    int r = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+                    while (r * (r + 1) / 2 > e)
+                        --r;
+                    while ((r + 1) * (r + 2) / 2 <= e)
+                        ++r;
+                    R = I + 1 + r;
+                    C = I + 1 + (e - r * (r + 1) / 2);
+                };
+                const int nwt = nw - 1;
+                for (int eb = wv; eb < ntile; eb += nwt * TB) {
+                    cx<T> cur[TB][4];
+#pragma unroll
+                    for (int b = 0; b < TB; ++b) {
+                        const int e = eb + nwt * b;
+                        int R = I + 1, C = I + 1;
+                        if (e < ntile)
+                            tile_rc(e, R, C);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = 16 * R + MF<T>::row(kr, v), j = 16 * C + cc;
+                            cur[b][v] = cur_el(I, i, j, e < ntile && i < m && j <= i);
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < TB; ++b) {
+                        const int e = eb + nwt * b;
+                        if (e >= ntile)
+                            break;
+                        int R, C;
+                        tile_rc(e, R, C);
+                        Acc3<T, 1, 1, RE> acc;
+                        acc.zero();
+                        const int ta = (R - I - 1) * 256 + cc * 16 + kr, tb = (C - I - 1) * 256 + cc * 16 + kr;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const cx<T> a = sP[ta + 4 * q], bb = sP[tb + 4 * q];
+                            acc.step(0, 0, a.r, a.i, bb.r, -bb.i);
+                        }
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = 16 * R + MF<T>::row(kr, v), j = 16 * C + cc;
+                            if (i < m && j <= i)
+                                Lg[(int64_t)i * m + j] =
+                                    cx<T>{cur[b][v].r - acc.re(0, 0, v), cur[b][v].i - acc.im(0, 0, v)};
+                        }
+                    }
+                }
             }
-        };
-        int e = wv;
-        cx<T> cur[4];
-        if (e < ntile)
-            load_tile(e, cur);
-        for (; e < ntile; e += nw) {
-            cx<T> nxt[4] = {czero<T>(), czero<T>(), czero<T>(), czero<T>()};
-            if (e + nw < ntile)
-                load_tile(e + nw, nxt);
-            int R, C;
-            tile_rc(e, R, C);
-            Acc3<T, 1, 1, RE> acc;
-            acc.zero();
-            // operands from LDS: two contraction steps per load group suffice
-            wave_mm3<T, 1, 1, false, true, 2, RE>(acc, WOp<T>{sP + (R - I - 1) * 256, 16, 1, 16},
-                                                  WOp<T>{sP + (C - I - 1) * 256, 16, 1, 16}, kd);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = 16 * R + MF<T>::row(kr, v), j = 16 * C + cc;
-                if (i < m && j <= i)
-                    Lg[(int64_t)i * m + j] = cx<T>{cur[v].r - acc.re(0, 0, v), cur[v].i - acc.im(0, 0, v)};
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                cur[v] = nxt[v];
         }
         __syncthreads();
     }
+    if (wv == 0 && lane == 0 && fail)
+        sFail = 1;
+    __syncthreads();
     if (tid == 0 && sFail)
         atomicMin(&flags[s.sys], fail_key(s.level, s.ob0 + s.obs * p));
 }
