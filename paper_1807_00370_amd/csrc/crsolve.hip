@@ -445,8 +445,11 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
             const int ngrp = (ns + NC - 1) / NC;
             Timed tm(c.p, KID_TRSM, c.st, L.cls, L.f64);
             if (sizeof(T) == 8 && L.total >= kTrsmStripBlocks && L.cls == kBig)
-                hipLaunchKernelGGL((crs::k_trsm_strip<T, EI, RE, 1>), dim3(grid8(L.total * ns)), dim3(64), 0,
-                                   c.st, c.dsegs + L.seg0, L.nseg, L.total, ns, mat, rhs,
+                // the real form's single-MFMA steps take the deeper prefetch
+                // (Poisson real form k_trsm 13.5 -> 13.2 ms; the complex form
+                // measured slower with it, 14.0 -> 14.7 ms)
+                hipLaunchKernelGGL((crs::k_trsm_strip<T, EI, RE, 1, RE ? 8 : 0>), dim3(grid8(L.total * ns)),
+                                   dim3(64), 0, c.st, c.dsegs + L.seg0, L.nseg, L.total, ns, mat, rhs,
                                    (const EI*)inB, (const EI*)iny, (cx<T>*)c.ws, c.flags);
             else if (sizeof(T) == 8 && L.cls == kBig)
                 // few blocks: every strip's chain of loads in flight eight

@@ -124,3 +124,14 @@ def test_noalloc_limits_checked_before_device_work():
     assert small.ws_bytes <= (256 << 20)
     hdr = open(os.path.join(ROOT, "include", "crsolve.h")).read()
     assert "256 MiB" in hdr
+
+
+def test_pcr_tail_default_by_block_size():
+    """The binding's default switch to Algorithm 1 follows the plan's largest
+    block: 64 blocks up to m = 32, 16 up to m = 64, 8 above."""
+    from paper_1807_00370_amd.solver import pcr_tail_default
+    assert pcr_tail_default([1]) == 64 and pcr_tail_default([32]) == 64
+    assert pcr_tail_default([33]) == 16 and pcr_tail_default([64]) == 16
+    assert pcr_tail_default([65]) == 8 and pcr_tail_default([256]) == 8
+    assert pcr_tail_default([8, 16, 100, 32]) == 8
+    assert pcr_tail_default([8, 40]) == 16
