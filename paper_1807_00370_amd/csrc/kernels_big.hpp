@@ -94,10 +94,10 @@ __device__ __forceinline__ void wave_mm(typename MF<T>::v4 (&cr)[RM][RN],
             const bool ok = 4 * ks + kr < kd;
 #pragma unroll
             for (int i = 0; i < RM; ++i)
-                xa[i][u] = (ok && oa[i]) ? pa[i][ks * sa] : czero<T>();
+                xa[i][u] = ld_or0(pa[i] + ks * sa, A.p, ok && oa[i]);
 #pragma unroll
             for (int j = 0; j < RN; ++j)
-                yb[j][u] = (ok && ob[j]) ? pb[j][ks * sb] : czero<T>();
+                yb[j][u] = ld_or0(pb[j] + ks * sb, B.p, ok && ob[j]);
         }
     };
     auto comp = [&](const cx<T>(&xa)[RM][G], const cx<T>(&yb)[RN][G]) {
@@ -164,10 +164,10 @@ __device__ __forceinline__ void wave_mm3(Acc3<T, RM, RN, RE>& acc, const WOp<T> 
             const bool ok = 4 * ks + kr < kd;
 #pragma unroll
             for (int i = 0; i < RM; ++i)
-                xa[i][u] = (ok && oa[i]) ? pa[i][ks * sa] : czero<T>();
+                xa[i][u] = ld_or0(pa[i] + ks * sa, A.p, ok && oa[i]);
 #pragma unroll
             for (int j = 0; j < RN; ++j)
-                yb[j][u] = (ok && ob[j]) ? pb[j][ks * sb] : czero<T>();
+                yb[j][u] = ld_or0(pb[j] + ks * sb, B.p, ok && ob[j]);
         }
     };
     auto comp = [&](const cx<T>(&xa)[RM][G], const cx<T>(&yb)[RN][G]) {
@@ -235,13 +235,10 @@ __device__ __forceinline__ void wave_mm_herm(typename MF<T>::v4& cr, typename MF
         for (int u = 0; u < G; ++u) {
             const int ks = g * G + u, t = 4 * ks + kr;
             const bool ok = t < kd;
-            cx<T> a = czero<T>();
-            if (ok && oa) {
-                a = A[t <= i ? i * m + t : t * m + i];
-                a.i = t < i ? a.i : (t == i ? T(0) : -a.i);
-            }
+            cx<T> a = ld_or0(A + (t <= i ? i * m + t : t * m + i), A, ok && oa);
+            a.i = t < i ? a.i : (t == i ? T(0) : -a.i);
             xa[u] = a;
-            yb[u] = (ok && ob) ? pb[ks * sb] : czero<T>();
+            yb[u] = ld_or0(pb + ks * sb, B.p, ok && ob);
         }
     };
     auto comp = [&](const cx<T>(&xa)[G], const cx<T>(&yb)[G]) {

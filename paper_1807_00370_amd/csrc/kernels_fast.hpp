@@ -63,6 +63,18 @@ __device__ __forceinline__ cx<T> czero()
     return cx<T>{T(0), T(0)};
 }
 
+// *p where ok, else zero.  The load is issued in every lane (from q, a valid
+// address, where ok is false), so no branch surrounds it and the compiler's
+// count of the wave's memory operations in flight stays exact: a wait for
+// one group of a software pipeline's loads then does not also wait for the
+// group issued after it.
+template <class T>
+__device__ __forceinline__ cx<T> ld_or0(const cx<T>* p, const cx<T>* q, bool ok)
+{
+    const cx<T> v = *(ok ? p : q);
+    return ok ? v : czero<T>();
+}
+
 // 1 / sqrt(d) from the hardware reciprocal square root and one Newton step
 // (relative error about the unit roundoff); NaN for d < 0, inf for d = 0.
 __device__ __forceinline__ double rsqrt_nr(double d)

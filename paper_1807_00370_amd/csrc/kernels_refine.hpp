@@ -99,14 +99,11 @@ __device__ __forceinline__ void wave_mm_herm_r(typename MF<T>::v4 (&cr)[RM][1],
 #pragma unroll
             for (int a = 0; a < RM; ++a) {
                 const int i = row0 + 16 * a + cc;
-                cx<T> v = czero<T>();
-                if (t < m && i < m) {
-                    v = A[t <= i ? i * m + t : t * m + i];
-                    v.i = t < i ? v.i : (t == i ? T(0) : -v.i);
-                }
+                cx<T> v = ld_or0(A + (t <= i ? i * m + t : t * m + i), A, t < m && i < m);
+                v.i = t < i ? v.i : (t == i ? T(0) : -v.i);
                 xa[a][u] = v;
             }
-            yb[u] = (t < m && ob) ? pb[(g * G + u) * sb] : czero<T>();
+            yb[u] = ld_or0(pb + (g * G + u) * sb, B.p, t < m && ob);
         }
     };
     auto comp = [&](const cx<T>(&xa)[RM][G], const cx<T>(&yb)[G]) {
@@ -182,20 +179,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         cx<T> acc = czero<T>();
 #pragma unroll 4
         for (int tt = kr; tt < m; tt += 4) {
-            cx<T> hv = czero<T>(), bm = czero<T>(), bp = czero<T>();
-            if (oi) {
-                hv = Aj[tt <= i ? i * m + tt : tt * m + i];
-                hv.i = tt < i ? hv.i : (tt == i ? T(0) : -hv.i);
-                if (hasM)
-                    bm = Bm[i * m + tt];
-                if (hasP) {
-                    bp = Bj[tt * m + i];
-                    bp.i = -bp.i; // (B_j^H)[i][t] = conj(B_j[t][i])
-                }
-            }
+            cx<T> hv = ld_or0(Aj + (tt <= i ? i * m + tt : tt * m + i), Aj, oi);
+            hv.i = tt < i ? hv.i : (tt == i ? T(0) : -hv.i);
+            const cx<T> bm = ld_or0(Bm + i * m + tt, Aj, oi && hasM);
+            cx<T> bp = ld_or0(Bj + tt * m + i, Aj, oi && hasP);
+            bp.i = -bp.i; // (B_j^H)[i][t] = conj(B_j[t][i])
             const cx<T> x0 = xj[tt];
-            const cx<T> xm = hasM ? xj[tt - mk] : czero<T>();
-            const cx<T> xp = hasP ? xj[tt + mk] : czero<T>();
+            const cx<T> xm = ld_or0(xj + tt - mk, xj, hasM);
+            const cx<T> xp = ld_or0(xj + tt + mk, xj, hasP);
             acc.r += hv.r * x0.r - hv.i * x0.i + bm.r * xm.r - bm.i * xm.i + bp.r * xp.r -
                      bp.i * xp.i;
             acc.i += hv.r * x0.i + hv.i * x0.r + bm.r * xm.i + bm.i * xm.r + bp.r * xp.i +
