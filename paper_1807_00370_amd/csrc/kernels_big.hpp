@@ -278,16 +278,6 @@ __device__ __forceinline__ void zero_acc(typename MF<T>::v4 (&cr)[RM][RN],
         }
 }
 
-// Orders the LDS accesses of one wave: stores before the call are seen by
-// loads after it from any lane of the same wave (a wave's LDS operations
-// complete in order; the fences keep the compiler from moving them).
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // The diagonal step of panel I of the tiled Cholesky, run by one wave: the
 // tile S_II (lower triangle in sT, leading dimension 17) is factored by the
 // left-looking lane-per-row Cholesky, lane r & 15 keeping row r in registers

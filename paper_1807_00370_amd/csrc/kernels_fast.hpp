@@ -106,6 +106,51 @@ __device__ __forceinline__ cx<T> lane_bcast(const cx<T> x, int l)
     return cx<T>{lane_bcast(x.r, l), lane_bcast(x.i, l)};
 }
 
+// Orders the LDS accesses of one wave: stores before the call are seen by
+// loads after it from any lane of the same wave (a wave's LDS operations
+// complete in order; the fences keep the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// x[l] + x[l ^ 32] in every lane l, through the gfx950 swap of the upper
+// half of one register with the lower half of another (one VALU instruction
+// per dword, no LDS round trip).  Swapping x with itself leaves one result
+// holding the lower half's values in both halves and the other the upper
+// half's, so their sum is the same, bit for bit, in every lane.
+__device__ __forceinline__ float sum_xor32(float x)
+{
+    const unsigned v = __float_as_uint(x);
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double sum_xor32(double x)
+{
+    const unsigned long long v = (unsigned long long)__double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(v >> 32), (unsigned)(v >> 32), false, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+// x[l] + x[l ^ 16], the same way with the swap of odd and even 16-lane rows.
+__device__ __forceinline__ float sum_xor16(float x)
+{
+    const unsigned v = __float_as_uint(x);
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double sum_xor16(double x)
+{
+    const unsigned long long v = (unsigned long long)__double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(v >> 32), (unsigned)(v >> 32), false, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
 // MFMA 16x16x4 lane layout (wave64, checked on gfx950): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register v of lane l
 // holds D[row][l % 16] with row = 4 (l / 16) + v for the f32 instruction and
@@ -191,8 +236,8 @@ __device__ __forceinline__ void tile_hn(typename MF<T>::v4& cr, typename MF<T>::
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int ks = g * G + u, t = 4 * ks + kr;
-            xa[b][u] = (t < kd && okx) ? xb[ks * sx] : czero<T>();
-            yb[b][u] = (t < kd && oky) ? yq[ks * sy] : czero<T>();
+            xa[b][u] = ld_or0(xb + ks * sx, X, t < kd && okx);
+            yb[b][u] = ld_or0(yq + ks * sy, Y, t < kd && oky);
         }
     };
     load(0, 0);
@@ -232,8 +277,8 @@ __device__ __forceinline__ void tile_nn(typename MF<T>::v4& cr, typename MF<T>::
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int ks = g * G + u, t = 4 * ks + kr;
-            xa[b][u] = (t < kd && okx) ? xb[4 * ks] : czero<T>();
-            yb[b][u] = (t < kd && oky) ? yq[ks * sy] : czero<T>();
+            xa[b][u] = ld_or0(xb + 4 * ks, X, t < kd && okx);
+            yb[b][u] = ld_or0(yq + ks * sy, Y, t < kd && oky);
         }
     };
     load(0, 0);
@@ -271,8 +316,8 @@ __device__ __forceinline__ void tile_nn3(Acc3<T, 1, 1>& acc, const cx<T>* __rest
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int ks = g * G + u, t = 4 * ks + kr;
-            xa[b][u] = (t < kd && okx) ? xb[4 * ks] : czero<T>();
-            yb[b][u] = (t < kd && oky) ? yq[ks * sy] : czero<T>();
+            xa[b][u] = ld_or0(xb + 4 * ks, X, t < kd && okx);
+            yb[b][u] = ld_or0(yq + ks * sy, Y, t < kd && oky);
         }
     };
     load(0, 0);
@@ -578,63 +623,95 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             _Pragma("unroll") for (int v_ = 0; v_ < 4; ++v_)                                       \
             {                                                                                      \
                 const int r_ = 16 * I_ + MF<T>::row(kr, v_);                                       \
-                cx<T> x_ = czero<T>();                                                             \
-                if (okc_ && r_ < m)                                                                \
-                    x_ = cvt<T>(col_[r_ * sr_]);                                                   \
-                g[I_][v_] = cx<T>{x_.r, cj_ * x_.i};                                               \
+                const bool ok_ = okc_ && r_ < m;                                                   \
+                const cx<T> x_ = cvt<T>(col_[(ok_ ? r_ : 0) * sr_]);                               \
+                g[I_][v_] = ok_ ? cx<T>{x_.r, cj_ * x_.i} : czero<T>();                            \
             }                                                                                      \
     } while (0)
     cx<T> gn[S][4];
 
+    // a lane's elements e = lane + 64 q of the packed lower triangle, all
+    // loads issued before the first is used (one round trip, not NE); lanes
+    // past the end load and store the last element (the same value), so no
+    // branch holds a load back
+    constexpr int NE = (NP + 63) / 64;
     if (with_mat) {
         const EI* Ap = inA + s.oA + (int64_t)p * mm;
-        for (int e = lane; e < np; e += 64) {
-            const int r = tri_row(e), c = e - r * (r + 1) / 2;
-            sL[e] = cvt<T>(Ap[r * m + c]);
-        }
-        __syncthreads();
-        // left-looking Cholesky, one row per lane: lane c holds row c of L,
-        // whose finished entries reach every lane through the scalar
-        // registers (no LDS round trip or barrier per column)
-        cx<T> a[MT];
-        const int rl = lane < m ? lane : 0;
+        EI av[NE];
 #pragma unroll
-        for (int u = 0; u < MT; ++u)
-            a[u] = (u <= rl) ? sL[rl * (rl + 1) / 2 + u] : czero<T>();
+        for (int q = 0; q < NE; ++q) {
+            const int e = min(lane + 64 * q, np - 1), r = tri_row(e);
+            av[q] = Ap[r * m + e - r * (r + 1) / 2];
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            sL[min(lane + 64 * q, np - 1)] = cvt<T>(av[q]);
+        __syncthreads();
+        // left-looking Cholesky with each dot product split over the
+        // G = 64 / MT lane groups: lane g MT + r keeps the entries u = G j + g
+        // of row r (b[j]) and sums the terms u = g (mod G); the groups'
+        // partial sums meet by lane swaps.  Each finished entry L[r][c] goes
+        // to LDS in place of A's (row r is read only by its own lanes), from
+        // where every later column c' reads row c' by broadcast.
+        constexpr int G = 64 / MT, NB = MT / G;
+        const int r = lane % MT, grp = lane / MT;
+        const int rl = r < m ? r : 0;
+        cx<T> b[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int u = G * j + grp;
+            b[j] = (u <= rl) ? sL[rl * (rl + 1) / 2 + u] : czero<T>();
+        }
         bool fail = false;
 #pragma unroll
         for (int c = 0; c < MT; ++c) {
             if (c < m) {
-                cx<T> s0 = czero<T>(), s1 = czero<T>();
-                // dot product in chunks of 8 terms (bounds the scalar
-                // registers of the broadcast row entries in flight)
+                // row c of L (entries u < c final): every read issued before
+                // the first product, so the LDS latency is paid once a column
+                const cx<T>* rc = sL + c * (c + 1) / 2;
+                cx<T> lc[NB];
 #pragma unroll
-                for (int u = 0; u + 1 < c; u += 2) {
-                    msub_cb(s0, a[u], lane_bcast(a[u], c));
-                    msub_cb(s1, a[u + 1], lane_bcast(a[u + 1], c));
-                    if ((u & 7) == 6)
-                        __builtin_amdgcn_sched_barrier(0);
+                for (int j = 0; j < c / G; ++j)
+                    lc[j] = rc[G * j + grp];
+                if (c % G) // groups g >= c mod G read entry 0 and add zero
+                    lc[c / G] = rc[grp < c % G ? G * (c / G) + grp : 0];
+                __builtin_amdgcn_sched_barrier(0);
+                cx<T> s0 = czero<T>(), s1 = czero<T>();
+#pragma unroll
+                for (int j = 0; j < c / G; ++j) {
+                    if (j & 1)
+                        msub_cb(s1, b[j], lc[j]);
+                    else
+                        msub_cb(s0, b[j], lc[j]);
                 }
-                if (c & 1)
-                    msub_cb(s0, a[c - 1], lane_bcast(a[c - 1], c));
-                const cx<T> v{a[c].r + s0.r + s1.r, a[c].i + s0.i + s1.i};
-                const T dg = lane_bcast(v.r, c);
+                if (c % G) { // the last terms: groups g < c mod G only
+                    const int j = c / G;
+                    msub_cb(s0, grp < c % G ? b[j] : czero<T>(), lc[j]);
+                }
+                cx<T> sm{s0.r + s1.r, s0.i + s1.i};
+                if (G == 4) {
+                    sm.r = sum_xor16(sm.r);
+                    sm.i = sum_xor16(sm.i);
+                }
+                sm.r = sum_xor32(sm.r);
+                sm.i = sum_xor32(sm.i);
+                // group c mod G holds entry c of every row
+                const int gc = c % G, jc = c / G;
+                const cx<T> v{b[jc].r + sm.r, b[jc].i + sm.i};
+                const T dg = lane_bcast(v.r, gc * MT + c);
                 const T inv = rsqrt_nr(dg);
                 const T sq = dg * inv;
                 fail |= !(dg > T(0));
-                if (lane == c)
-                    a[c] = cx<T>{sq, inv}; // inverse pivot kept in the imaginary slot
-                else
-                    a[c] = cx<T>{v.r * inv, v.i * inv};
+                // inverse pivot kept in the imaginary slot of the diagonal
+                const cx<T> l = r == c ? cx<T>{sq, inv} : cx<T>{v.r * inv, v.i * inv};
+                if (grp == gc) {
+                    b[jc] = l;
+                    if (r >= c && r < m)
+                        sL[r * (r + 1) / 2 + c] = l;
+                }
+                wave_lds_sync();
             }
             __builtin_amdgcn_sched_barrier(0);
-        }
-        __syncthreads(); // every lane has read its row of A from LDS
-        if (lane < m) {
-#pragma unroll
-            for (int u = 0; u < MT; ++u)
-                if (u <= lane)
-                    sL[lane * (lane + 1) / 2 + u] = a[u];
         }
         __syncthreads();
         if (lane == 0)
@@ -646,8 +723,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 Lg[e] = sL[e];
         }
     } else {
-        for (int e = lane; e < np; e += 64)
-            sL[e] = Lg[e];
+        cx<T> lv[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            lv[q] = Lg[min(lane + 64 * q, np - 1)];
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            sL[min(lane + 64 * q, np - 1)] = lv[q];
     }
     __syncthreads();
 
@@ -676,8 +758,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 g[I][v] = gn[I][v];
-        if (st + nsplit < nst)
-            CRS_LOAD_STRIP(st + nsplit, gn);
+        // the next strip (the current one again after the last): issued in
+        // every pass, so the wait for this strip's loads does not wait for it
+        CRS_LOAD_STRIP(st + nsplit < nst ? st + nsplit : st, gn);
         // X_0 = D_0 G_0 (3M products, combined before they chain on)
         v4 x0r, x0i;
         {
@@ -1136,8 +1219,19 @@ __global__ __launch_bounds__(64, 2) void k_back_mf(const Seg* __restrict__ segs,
     const cx<T>* P = W + s.oP + t * mm;
     const cx<T>* Q = W + s.oQ + t * mm;
     const cx<T>* g = W + s.og + t * mk;
-    for (int e = lane; e < m * (m + 1) / 2; e += 64)
-        sL[e] = L[e];
+    {
+        // packed L: a lane's NE elements loaded together (lanes past the end
+        // load and store the last one), one round trip
+        constexpr int NE = (NP + 63) / 64;
+        const int np = m * (m + 1) / 2;
+        cx<T> lv[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            lv[q] = L[min(lane + 64 * q, np - 1)];
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            sL[min(lane + 64 * q, np - 1)] = lv[q];
+    }
     __syncthreads();
     // left operands: (L_10^H)[i][u] = conj(L[16 + u][i]), then (D_I^H)[i][u] =
     // conj(D_I[u][i])
