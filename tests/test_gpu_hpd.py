@@ -1,7 +1,7 @@
 """The positive-definiteness test (GPU): crsolve_check_hpd against the
 smallest eigenvalue of the assembled dense matrix, and its (level, block)
-against the oracle's, for the three kernel families (m <= 8, 8 < m <= 32,
-tiled m > 32).  Each matrix is shifted by c I so that its smallest
+against the oracle's, for the three kernel families (m <= 8, 8 < m <= 32
+with its four-group and two-group Cholesky, tiled m > 32).  Each matrix is shifted by c I so that its smallest
 eigenvalue is +0.05 or -0.05: far enough from zero for the verdict to be
 exact (the flag near the boundary is rounding-dependent)."""
 import numpy as np
@@ -32,7 +32,7 @@ def _dense(A, B):
     return M
 
 
-@pytest.mark.parametrize("N,m", [(12, 3), (9, 12), (7, 40)])
+@pytest.mark.parametrize("N,m", [(12, 3), (9, 12), (10, 24), (8, 32), (7, 40)])
 @pytest.mark.parametrize("sign", [1, -1])
 def test_check_hpd_matches_eigenvalues(tdev, N, m, sign):
     torch, dev = tdev
