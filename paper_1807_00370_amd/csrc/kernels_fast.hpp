@@ -13,8 +13,9 @@
 //               form), operands loaded from HBM straight into the MFMA lane
 //               layout; diagonal blocks are written as their lower triangle
 //               only (the Hermitian reading every consumer uses).
-//   k_elim_mf   (8 < m <= 32) the same Cholesky, then the substitutions on
-//               MFMA with the inverses of the 16 x 16 diagonal tiles.
+//   k_elim_mf   (8 < m <= 32) the Cholesky with each row's dot products
+//               split over the wave's lane groups, then the substitutions
+//               on MFMA with the inverses of the 16 x 16 diagonal tiles.
 //   k_back_mf   w = g - Q x_{p-d} - P x_{p+d} on MFMA, then L^H x = w tile by
 //               tile on MFMA with the inverse diagonal tiles.
 #pragma once
@@ -549,9 +550,10 @@ __device__ __forceinline__ void inverse_tiles_lds(cx<T>* sL, int m)
 // ---------------------------------------------------------------- k_elim_mf
 
 // Elimination for block sizes 8 < m <= 32 with the forward substitutions on
-// MFMA.  After the Cholesky (as in k_elim_w) the inverses D_I = L_II^{-1} of
-// the 16 x 16 diagonal tiles are formed, and each 16-column strip G of
-// [B_p^H | B_{p-d} | y_p] is solved tile by tile, X_0 = D_0 G_0 and
+// MFMA.  After the Cholesky (its dot products split over the lane groups) the
+// inverses D_I = L_II^{-1} of the 16 x 16 diagonal tiles are formed, and each
+// 16-column strip G of [B_p^H | B_{p-d} | y_p] is solved tile by tile,
+// X_0 = D_0 G_0 and
 // X_1 = D_1 (G_1 - L_10 X_0): register v of a lane's accumulator holds row
 // MF::row(kr, v) of its column, which is the right operand of contraction
 // step v when the left operand supplies column MF::row(kr, v), so the
