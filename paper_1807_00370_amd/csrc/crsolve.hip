@@ -425,8 +425,10 @@ void run_elim(const Ctx& c, const Launch& L, const void* A, const void* B, const
             // levels with at most one block per CU spread the panel tiles over
             // eight waves instead of four
             const unsigned nthr = L.total <= kPotrfWideBlocks ? 512 : 256;
-            if (L.cls == kBig && L.total <= kPotrfWideBlocks)
-                // few blocks: one block's chain of panels sets the time
+            if (L.total <= kPotrfWideBlocks)
+                // few blocks (every tiled class): one block's chain of panels
+                // sets the time, so the diagonal steps run ahead of the
+                // trailing updates
                 hipLaunchKernelGGL((crs::k_potrf_rl<T, EI, RE>), dim3((unsigned)L.total), dim3(512), 0,
                                    c.st, c.dsegs + L.seg0, L.nseg, L.total, (const EI*)inA,
                                    (cx<T>*)c.ws, c.flags);
