@@ -60,7 +60,7 @@ def _solve(torch, dev, s, schedule="cr", dtype=None):
 
 CASES = [(1, 5, 3), (2, 3, 1), (3, 4, 2), (5, 2, 2), (64, 4, 1), (64, 1, 1), (1000, 6, 3),
          (777, 16, 16), (513, 32, 16), (300, 64, 32), (129, 8, 16), (50, 17, 5), (33, 64, 1),
-         (257, 3, 7)]
+         (257, 3, 7), (1, 24, 3), (2, 12, 17), (3, 32, 1), (7, 9, 2), (31, 29, 33)]
 
 
 @pytest.mark.parametrize("N,m,k", CASES)
@@ -76,7 +76,7 @@ def test_cr_matches_oracle(torch_dev, N, m, k):
 
 
 @pytest.mark.parametrize("N,m,k", [(1, 4, 1), (2, 3, 2), (7, 4, 1), (64, 4, 1), (100, 8, 3),
-                                   (255, 16, 4), (130, 32, 16), (40, 64, 2)])
+                                   (255, 16, 4), (130, 32, 16), (40, 64, 2), (5, 24, 17)])
 def test_pcr_matches_oracle(torch_dev, N, m, k):
     torch, dev = torch_dev
     print("case pcr N=%d m=%d k=%d" % (N, m, k), flush=True)
